@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the fast adaptive bilateral filter on one MI355X.
+
+A step is one pass of the whole fast filter (window bounds, moment stack,
+range stage) over one synthetic image already resident in HBM, issued as
+the three C-ABI calls abf_minmax -> abf_stack_moments -> abf_range on one
+stream (exactly what abf_fast does), with HIP events between them so each
+kernel group is timed live. The mixed-precision path is the headline
+value; the all-FP64 path and the GPU brute force are timed beside it, and
+parity against the CPU oracle is checked on sampled pixels.
+
+Prints ONE JSON line (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fast-ABF mixed vs all-FP64 on GPU at max err≤0.05/255; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
+DEFAULT_WORKLOAD = "sharpen1024_gauss15_n6"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
+    """Algorithmic bytes and FP64 flops per launch for each kernel group.
+
+    bytes: the inputs a kernel must read and the outputs it must write,
+    once each (halo re-reads and intermediates are overhead, not counted).
+    flops: the minimal FP64 arithmetic of the method's formulas.
+    """
+    px = h * w
+    b = prec_bytes
+    tb = 4 if theta_given else 4     # theta plane, or f when theta = f
+    win = 2 * R + 1
+    conv_flops = (4 * N * win) if kernel == "gaussian" else (4 * N)   # two separable passes
+    shift_flops = N * (N + 1) + 2 * N + (N * N) // 2                  # Prop. 3 shift, scale, Legendre
+    range_flops = (N + 1) * (N + 2) + 8 * (N + 1) + 20                # fit, recursion, T1/T2, t0/lambda
+    return {
+        "minmax": dict(bytes=px * (4 + 8), flops=0),
+        "moments": dict(bytes=px * (4 + 8 + N * b), flops=px * (conv_flops + shift_flops)),
+        "range": dict(bytes=px * (8 + N * b + tb + 4 + b), flops=px * range_flops),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--parity-pixels", type=int, default=600)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1811_02308_amd as abf
+    from synth import workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    abf.lib()
+    wl = workload(args.workload)
+    f, th, sg = wl["f"], wl["theta"], wl["sigma"]
+    H, W = f.shape
+    R, N, kernel, ss = wl["R"], wl["N"], wl["kernel"], wl["sigma_s"]
+    log(f"workload {args.workload}: {H}x{W} {kernel} R={R} N={N}")
+
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    fd, td, sd = dev(f), dev(th), dev(sg)
+    scratch = torch.empty(abf.lib().abf_scratch_bytes(H, W, R), dtype=torch.uint8, device="cuda")
+
+    def make_path(prec):
+        stack = torch.empty(abf.stack_bytes(H, W, N, prec), dtype=torch.uint8, device="cuda")
+        out = torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64, device="cuda")
+
+        def step(ev=None):
+            if ev is not None:
+                ev[0].record()
+            abf.minmax_into_stack(fd, stack, R, N, prec, workspace=scratch)
+            if ev is not None:
+                ev[1].record()
+            abf.stack_moments(fd, stack, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec)
+            if ev is not None:
+                ev[2].record()
+            abf.range_from_stack(stack, sd, img=fd, theta=td, N=N, precision=prec, out=out)
+            if ev is not None:
+                ev[3].record()
+
+        return out, step
+
+    def time_path(prec, steps, warmup):
+        out, step = make_path(prec)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        # K steps issued back to back on one stream, synchronised on both sides
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(evs[i])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        stage_ms = {"minmax": [e[0].elapsed_time(e[1]) for e in evs],
+                    "moments": [e[1].elapsed_time(e[2]) for e in evs],
+                    "range": [e[2].elapsed_time(e[3]) for e in evs]}
+        total_ms = [e[0].elapsed_time(e[3]) for e in evs]
+        return out, stage_ms, total_ms, wall
+
+    # ---------------------------------------------------------- timed region
+    log("timing mixed path ...")
+    out_m, st_m, tot_m, wall_m = time_path("mixed", args.steps, args.warmup)
+    log("timing fp64 path ...")
+    out_d, st_d, tot_d, wall_d = time_path("fp64", args.steps, args.warmup)
+
+    med = lambda v: float(np.median(v))
+    # whole-job rate: K steps over the synchronised wall clock of the timed region
+    ms_m, ms_d = wall_m, wall_d
+    mpix = H * W / 1e6
+    value = mpix / (ms_m * 1e-3)
+    value_d = mpix / (ms_d * 1e-3)
+
+    # brute force on the GPU (context)
+    log("timing GPU brute force ...")
+    bsteps = 3
+    ob = abf.bruteforce(fd, sd, theta=td, kernel=kernel, rho=R, sigma_s=ss, precision="fp64")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(bsteps):
+        abf.bruteforce(fd, sd, theta=td, kernel=kernel, rho=R, sigma_s=ss, precision="fp64", out=ob)
+    e1.record()
+    torch.cuda.synchronize()
+    brute_ms = e0.elapsed_time(e1) / bsteps
+
+    # ---------------------------------------------------------- parity (sampled)
+    import oracle
+    rng = np.random.default_rng(7)
+    n = args.parity_pixels
+    ys = np.concatenate([rng.integers(0, H, n), [0, 0, H - 1, H - 1]])
+    xs = np.concatenate([rng.integers(0, W, n), [0, W - 1, 0, W - 1]])
+    log("oracle parity on sampled pixels ...")
+    ref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(ys, xs))
+    gm = out_m.cpu().numpy().astype(np.float64)[ys, xs]
+    gd = out_d.cpu().numpy()[ys, xs]
+    err_m = float(np.max(np.abs(gm - ref)))
+    err_d = float(np.max(np.abs(gd - ref)))
+
+    # ---------------------------------------------------------- roofline
+    model = stage_model(H, W, kernel, R, N, 4, th is not None)
+    stages = {k: med(v) for k, v in st_m.items()}
+    dom = max(stages, key=stages.get)
+    dur_s = stages[dom] * 1e-3
+    gbs = model[dom]["bytes"] / dur_s / 1e9
+    tfl = model[dom]["flops"] / dur_s / 1e12
+    frac_h = gbs / HBM_PEAK_GBS
+    frac_a = tfl / FP64_PEAK_TFLOPS
+    if frac_a > frac_h:
+        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(frac_a, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(frac_h, 4)}
+    roof.update({"kernel": dom, "traffic": None, "launch_ms": round(stages[dom], 5),
+                 "algorithmic_bytes": model[dom]["bytes"], "algorithmic_flops": model[dom]["flops"]})
+
+    # ---------------------------------------------------------- CPU oracle baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            from threadpoolctl import threadpool_limits
+        except Exception:                      # pragma: no cover
+            threadpool_limits = None
+        ctx = threadpool_limits(1) if threadpool_limits else None
+        try:
+            probe = 500
+            t0 = time.perf_counter()
+            oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss,
+                            pixels=(rng.integers(0, H, probe), rng.integers(0, W, probe)))
+            per_px = (time.perf_counter() - t0) / probe
+            m = int(max(probe, min(H * W, args.cpu_seconds / max(per_px, 1e-9))))
+            sy, sx = rng.integers(0, H, m), rng.integers(0, W, m)
+            t0 = time.perf_counter()
+            oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(sy, sx))
+            dt = time.perf_counter() - t0
+            cpu = {"value": round(m / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{m} random pixels of the same {H}x{W} workload, value-of-record "
+                             f"oracle route, 1 thread, {dt:.1f} s"}
+        finally:
+            if ctx is not None:
+                ctx.__exit__(None, None, None)
+
+    lat_m = np.array(tot_m)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_m, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "h": H, "w": W, "kernel": kernel, "rho": R, "N": N,
+                   "sigma_s": ss, "precision": "mixed (FP64 arithmetic, FP32 stack and output)"},
+        "latency_ms": {"p50": round(float(np.percentile(lat_m, 50)), 5),
+                       "p99": round(float(np.percentile(lat_m, 99)), 5)},
+        "stage_ms_mixed": {k: round(v, 5) for k, v in stages.items()},
+        "fp64": {"value": round(value_d, 2), "ms_per_step": round(ms_d, 5),
+                 "stage_ms": {k: round(med(v), 5) for k, v in st_d.items()},
+                 "max_abs_err_vs_oracle": err_d},
+        "mixed_max_abs_err_vs_oracle": err_m,
+        "parity_pixels": int(len(ys)),
+        "brute_force_fp64": {"value": round(mpix / (brute_ms * 1e-3), 3), "ms": round(brute_ms, 3)},
+        "device_ms_per_step_median": {"mixed": round(med(tot_m), 5), "fp64": round(med(tot_d), 5)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * abf.h -- C ABI of the MI355X (gfx950) fast adaptive bilateral filter.
+ *
+ * Implements the filter of Gavaskar & Chaudhury, "Fast Adaptive Bilateral
+ * Filtering" (arXiv:1811.02308):
+ *
+ *   brute force  g(i) = sum_j w(j) phi_i(f(i-j) - theta(i)) f(i-j) / eta(i)
+ *                eqs. (BF_adaptive1), (BF_adaptive2), (r_kernel)
+ *   fast         Algorithm 1 (Sec. II-D): window bounds alpha, beta
+ *                (eq. bounds), moments of the local histogram by
+ *                convolution (Prop. 2), the shift to [alpha, beta]
+ *                (Prop. 3), the Hilbert-inverse fit (Theorem, eq. inv),
+ *                the range integrals I_k (eqs. I_0, I_1, F_forward) and the
+ *                ratio of eq. (BFfinal).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Images are single-channel, row-major float32 planes on the DEVICE,
+ *   h rows by w columns; `pitch` is the distance between rows in elements
+ *   (pitch >= w). The caller owns every buffer; the library never frees or
+ *   keeps a pointer after a call returns.
+ * - Border rule: windows are clamp-to-edge (replicate) in every stage.
+ * - Window: `rho` is the integer radius R; the window is [-R, R]^2. The box
+ *   kernel weighs every tap 1/(2R+1)^2. The Gaussian kernel weighs tap j by
+ *   exp(-|j|^2 / (2 sigma_s^2)) (eq. sp_kernel), normalised to sum to 1;
+ *   sigma_s <= 0 selects sigma_s = R/3 (the paper's window [-3 rho, 3 rho]).
+ * - theta may be NULL, meaning theta = f (the classical filter, Sec. III).
+ *   sigma must hold values > 0 (or +inf, which gives the spatial mean);
+ *   this is not checked on the device, violations give NaN at that pixel.
+ * - All calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *   stream). Argument errors are reported synchronously, before any HIP
+ *   call, as ABF_E_INVALID / ABF_E_UNSUPPORTED / ABF_E_WORKSPACE; a failed
+ *   launch is reported as ABF_E_HIP. Nothing is synchronised.
+ * - Precision: ABF_PREC_FP64 computes and stores everything in FP64 and
+ *   writes a double output. ABF_PREC_MIXED computes in FP64 but keeps the
+ *   moment stack and the output in FP32 (see abf_moment_stack).
+ * - Calls on different streams with different workspaces may run
+ *   concurrently; the library holds no mutable device state.
+ */
+#ifndef ABF_H
+#define ABF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ABF_OK = 0,
+    ABF_E_INVALID = -1,      /* null pointer, bad size, pitch < w, ...      */
+    ABF_E_NOMEM = -2,        /* reserved (the library never allocates)      */
+    ABF_E_HIP = -3,          /* a HIP launch or runtime call failed         */
+    ABF_E_UNSUPPORTED = -4,  /* valid but outside what is built (N, rho)    */
+    ABF_E_WORKSPACE = -5     /* workspace/stack too small or misaligned     */
+} abf_status;
+
+enum { ABF_KERNEL_BOX = 0, ABF_KERNEL_GAUSSIAN = 1 };
+enum { ABF_PREC_FP64 = 0, ABF_PREC_MIXED = 1 };
+/* ABF_FLAG_CLAMP: clip the output to [alpha_i, beta_i] (the fitted
+ * polynomial may go negative, Sec. II-B); recommended, used by tests.     */
+enum { ABF_FLAG_CLAMP = 1u };
+enum { ABF_N_MAX = 8, ABF_RHO_MAX = 96 };
+
+/* Human-readable name of a status code (static string). */
+const char* abf_status_string(int status);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int abf_version(void);
+
+/*
+ * Moment stack (the resident intermediate of Algorithm 1).
+ * Layout: plane pitch P = abf_stack_pitch(w) elements (a multiple of 64);
+ *   plane 0  alpha_i  float32 (exact window minimum of f)
+ *   plane 1  beta_i   float32 (exact window maximum of f)
+ *   planes 2..N+1     a~_k, k = 1..N: the shifted-Legendre moments of the
+ *            stretched histogram H_i (eqs. Lambda_tilde, mhist),
+ *            a~_k = sum_j w(j) P_k(2 y_j - 1) with y_j = (f(i-j)-alpha_i)/
+ *            (beta_i-alpha_i); they equal sum_r ell_kr mu_r for the moments
+ *            mu_r of eq. (hist_moments_new), and lie in [-1, 1].
+ *            float32 for ABF_PREC_MIXED, float64 for ABF_PREC_FP64.
+ * Plane k starts at byte offset abf_stack_plane_offset(h, w, N, prec, k).
+ * Where alpha_i == beta_i the moment planes hold 0.
+ * The stack depends on (f, kernel, rho, N) only, not on theta or sigma.
+ */
+long long abf_stack_pitch(int w);
+size_t abf_stack_bytes(int h, int w, int N, int precision);
+size_t abf_stack_plane_offset(int h, int w, int N, int precision, int plane);
+
+/* Scratch needed by abf_fast / abf_moment_stack / abf_minmax besides the
+ * stack (bytes). abf_fast's workspace = abf_stack_bytes + this. */
+size_t abf_scratch_bytes(int h, int w, int rho);
+size_t abf_workspace_bytes(int h, int w, int rho, int N, int precision);
+
+/*
+ * abf_minmax -- eq. (bounds): alpha_i / beta_i = min / max of f over the
+ * clamp-to-edge window [-rho, rho]^2 (Algorithm 1, line 2; Prop. 1). Exact
+ * (bit-identical to any correct evaluation). alpha/beta: device float32
+ * planes with row pitch out_pitch. workspace: >= abf_scratch_bytes(h,w,rho)
+ * bytes, 256-byte aligned. rho in [0, ABF_RHO_MAX].
+ */
+abf_status abf_minmax(const float* img, int h, int w, long long pitch, int rho,
+                      float* alpha, float* beta, long long out_pitch,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * abf_moment_stack -- Algorithm 1 lines 2 and 6-9 (Props. 1-3): writes the
+ * moment stack described above into `stack` (>= abf_stack_bytes, 256-byte
+ * aligned). The power images are accumulated in FP64 about a local origin
+ * and shifted to [alpha_i, beta_i] per pixel. N in [0, ABF_N_MAX].
+ */
+abf_status abf_moment_stack(const float* img, int h, int w, long long pitch,
+                            int kernel_kind, double sigma_s, int rho, int N,
+                            int precision, void* stack, size_t stack_bytes,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * abf_stack_moments -- the second half of abf_moment_stack: given a stack
+ * whose planes 0 and 1 already hold alpha_i and beta_i for this image and
+ * rho (e.g. written by abf_minmax with out_pitch = abf_stack_pitch(w)),
+ * writes the moment planes 2..N+1 (Algorithm 1 lines 6-9, Props. 2-3).
+ * Needs no scratch. Lets a caller time or schedule the two spatial
+ * kernels separately; abf_moment_stack = abf_minmax + abf_stack_moments.
+ */
+abf_status abf_stack_moments(const float* img, int h, int w, long long pitch,
+                             int kernel_kind, double sigma_s, int rho, int N,
+                             int precision, void* stack, size_t stack_bytes,
+                             void* stream);
+
+/*
+ * abf_range -- Algorithm 1 lines 10-20 from a moment stack: the fit
+ * c = A^-1 mu (eq. inv, evaluated through the Legendre moments), t0 and
+ * lambda (eq. sub), the integrals I_0..I_{N+1} (eqs. I_0, I_1 and the
+ * recursion F_forward; for lambda below a threshold where that recursion
+ * loses accuracy, the same definite integrals by Gauss-Legendre
+ * quadrature), and g^ = alpha + (beta - alpha) T1/T2 (eq. BFfinal).
+ * img is read only when theta is NULL. If T2 <= 0 or the ratio is not
+ * finite the N = 0 estimate I_1/I_0 is used. Where alpha_i == beta_i the
+ * output is f(i) (lines 4-5). out: float32 (MIXED) or float64 (FP64) with
+ * row pitch out_pitch (elements).
+ */
+abf_status abf_range(const void* stack, size_t stack_bytes, const float* img,
+                     const float* theta, const float* sigma, int h, int w,
+                     long long pitch, int N, int precision, unsigned flags,
+                     void* out, long long out_pitch, void* stream);
+
+/*
+ * abf_fast -- the whole fast filter (Algorithm 1) on one image:
+ * abf_moment_stack into the front of `workspace`, then abf_range.
+ * workspace >= abf_workspace_bytes(h, w, rho, N, precision), 256-byte
+ * aligned. theta, sigma share `pitch` with img.
+ */
+abf_status abf_fast(const float* img, const float* theta, const float* sigma,
+                    int h, int w, long long pitch, int kernel_kind, double sigma_s,
+                    int rho, int N, int precision, unsigned flags,
+                    void* out, long long out_pitch,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * abf_bruteforce -- eqs. (BF_adaptive1), (BF_adaptive2) directly, O(rho^2)
+ * per pixel; the plain reference the fast path is compared with.
+ * ABF_PREC_FP64: FP64 arithmetic, double output. ABF_PREC_MIXED: FP32
+ * arithmetic, float output. The exponent of each window is shifted by its
+ * smallest value (the common factor cancels in the ratio).
+ */
+abf_status abf_bruteforce(const float* img, const float* theta, const float* sigma,
+                          int h, int w, long long pitch, int kernel_kind,
+                          double sigma_s, int rho, int precision,
+                          void* out, long long out_pitch, void* stream);
+
+/* One image (or one channel) of a batch. */
+typedef struct abf_request {
+    const float* img;
+    const float* theta;      /* NULL: theta = f */
+    const float* sigma;
+    int h, w;
+    long long pitch;
+    int kernel_kind;
+    double sigma_s;
+    int rho;
+    int N;
+    void* out;               /* float32 (MIXED) / float64 (FP64) */
+    long long out_pitch;
+} abf_request;
+
+/*
+ * abf_fast_batched -- abf_fast over n independent requests (images or
+ * colour channels of any sizes and parameters) in one call on one stream.
+ * workspace >= abf_batched_workspace_bytes(reqs, n, precision); each
+ * request's stack and scratch get their own 256-byte aligned slice.
+ */
+size_t abf_batched_workspace_bytes(const abf_request* reqs, int n, int precision);
+abf_status abf_fast_batched(const abf_request* reqs, int n, int precision,
+                            unsigned flags, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABF_H */

@@ -1,0 +1,316 @@
+"""MI355X (gfx950) fast adaptive bilateral filter: thin Python binding.
+
+Every function here marshals arguments for one C-ABI entry point of
+``libabf.so`` (declared in ``include/abf.h``) and runs nothing else: all
+filtering happens in the library's HIP kernels. PyTorch provides device
+memory and the current HIP stream. If the library is not built, calls
+raise ``RuntimeError``; there is no fallback path.
+
+Functions mirror the C names: ``fast`` (abf_fast), ``bruteforce``
+(abf_bruteforce), ``minmax`` (abf_minmax), ``moment_stack``
+(abf_moment_stack), ``range_from_stack`` (abf_range), ``fast_batched``
+(abf_fast_batched).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "lib", "library_path", "fast", "bruteforce", "minmax", "moment_stack",
+    "range_from_stack", "fast_batched", "minmax_into_stack", "stack_moments", "workspace_bytes", "stack_bytes",
+    "stack_planes", "Request", "KERNELS", "PRECISIONS", "ABFError",
+]
+
+KERNELS = {"box": 0, "gaussian": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+FLAG_CLAMP = 1
+N_MAX = 8
+RHO_MAX = 96
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class ABFError(RuntimeError):
+    pass
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libabf.so")
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("img", ctypes.c_void_p), ("theta", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+        ("h", ctypes.c_int), ("w", ctypes.c_int), ("pitch", ctypes.c_longlong),
+        ("kernel_kind", ctypes.c_int), ("sigma_s", ctypes.c_double), ("rho", ctypes.c_int),
+        ("N", ctypes.c_int), ("out", ctypes.c_void_p), ("out_pitch", ctypes.c_longlong),
+    ]
+
+
+def lib():
+    """Load libabf.so (built in-tree by ``paper_1811_02308_amd.build``)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_1811_02308_amd.build` (no fallback exists)")
+    L = ctypes.CDLL(path)
+    vp, i, ll, d, sz, u = (ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double,
+                           ctypes.c_size_t, ctypes.c_uint)
+    sig = {
+        "abf_status_string": ([i], ctypes.c_char_p),
+        "abf_version": ([], i),
+        "abf_stack_pitch": ([i], ll),
+        "abf_stack_bytes": ([i, i, i, i], sz),
+        "abf_stack_plane_offset": ([i, i, i, i, i], sz),
+        "abf_scratch_bytes": ([i, i, i], sz),
+        "abf_workspace_bytes": ([i, i, i, i, i], sz),
+        "abf_minmax": ([vp, i, i, ll, i, vp, vp, ll, vp, sz, vp], i),
+        "abf_moment_stack": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp, sz, vp], i),
+        "abf_stack_moments": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp], i),
+        "abf_range": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
+        "abf_fast": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, ll, vp, sz, vp], i),
+        "abf_bruteforce": ([vp, vp, vp, i, i, ll, i, d, i, i, vp, ll, vp], i),
+        "abf_batched_workspace_bytes": ([ctypes.POINTER(Request), i, i], sz),
+        "abf_fast_batched": ([ctypes.POINTER(Request), i, i, u, vp, sz, vp], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib().abf_status_string(status).decode()
+        raise ABFError(f"{what} failed: {msg} (status {status})")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _plane(t, name):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ABFError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or t.dim() != 2 or t.stride(1) != 1:
+        raise ABFError(f"{name} must be a 2-D float32 tensor with unit column stride")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(p):
+    if p not in PRECISIONS:
+        raise ABFError(f"precision must be one of {list(PRECISIONS)}")
+    return PRECISIONS[p]
+
+
+def _kind(k):
+    if k not in KERNELS:
+        raise ABFError(f"kernel must be one of {list(KERNELS)}")
+    return KERNELS[k]
+
+
+def _common_pitch(img, *others):
+    p = img.stride(0)
+    for o in others:
+        if o is not None and (o.shape != img.shape or o.stride(0) != p):
+            raise ABFError("theta/sigma must have the image's shape and row pitch")
+    return p
+
+
+def _alloc_bytes(nbytes, device):
+    torch = _torch()
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=device)
+
+
+def workspace_bytes(h, w, rho, N, precision="mixed"):
+    return int(lib().abf_workspace_bytes(h, w, rho, N, _prec(precision)))
+
+
+def stack_bytes(h, w, N, precision="mixed"):
+    return int(lib().abf_stack_bytes(h, w, N, _prec(precision)))
+
+
+def fast(img, sigma, theta=None, kernel="box", rho=3, N=5, sigma_s=0.0, precision="mixed",
+         clamp=True, out=None, workspace=None, stream=None):
+    """abf_fast: Algorithm 1 on one image. Returns ``out`` (float32 for
+    'mixed', float64 for 'fp64')."""
+    torch = _torch()
+    img, sigma, theta = _plane(img, "img"), _plane(sigma, "sigma"), _plane(theta, "theta")
+    h, w = img.shape
+    pitch = _common_pitch(img, sigma, theta)
+    p = _prec(precision)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+    need = lib().abf_workspace_bytes(h, w, rho, N, p)
+    if workspace is None:
+        workspace = _alloc_bytes(need, img.device)
+    st = lib().abf_fast(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
+                        float(sigma_s), int(rho), int(N), p, FLAG_CLAMP if clamp else 0,
+                        _ptr(out), out.stride(0), _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(st, "abf_fast")
+    return out
+
+
+def bruteforce(img, sigma, theta=None, kernel="box", rho=3, sigma_s=0.0, precision="fp64",
+               out=None, stream=None):
+    """abf_bruteforce: eqs. (BF_adaptive1), (BF_adaptive2) directly."""
+    torch = _torch()
+    img, sigma, theta = _plane(img, "img"), _plane(sigma, "sigma"), _plane(theta, "theta")
+    h, w = img.shape
+    pitch = _common_pitch(img, sigma, theta)
+    p = _prec(precision)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+    st = lib().abf_bruteforce(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
+                              float(sigma_s), int(rho), p, _ptr(out), out.stride(0), _stream(stream))
+    _check(st, "abf_bruteforce")
+    return out
+
+
+def minmax(img, rho, stream=None):
+    """abf_minmax: window bounds (alpha, beta) as two float32 planes."""
+    torch = _torch()
+    img = _plane(img, "img")
+    h, w = img.shape
+    a = torch.empty((h, w), dtype=torch.float32, device=img.device)
+    b = torch.empty_like(a)
+    ws = _alloc_bytes(lib().abf_scratch_bytes(h, w, rho), img.device)
+    st = lib().abf_minmax(_ptr(img), h, w, img.stride(0), int(rho), _ptr(a), _ptr(b), a.stride(0),
+                          _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "abf_minmax")
+    return a, b
+
+
+def moment_stack(img, kernel="box", rho=3, N=5, sigma_s=0.0, precision="mixed", stack=None,
+                 workspace=None, stream=None):
+    """abf_moment_stack: returns the raw stack buffer (uint8 tensor)."""
+    img = _plane(img, "img")
+    h, w = img.shape
+    p = _prec(precision)
+    if stack is None:
+        stack = _alloc_bytes(lib().abf_stack_bytes(h, w, N, p), img.device)
+    if workspace is None:
+        workspace = _alloc_bytes(lib().abf_scratch_bytes(h, w, rho), img.device)
+    st = lib().abf_moment_stack(_ptr(img), h, w, img.stride(0), _kind(kernel), float(sigma_s),
+                                int(rho), int(N), p, _ptr(stack), stack.numel(), _ptr(workspace),
+                                workspace.numel(), _stream(stream))
+    _check(st, "abf_moment_stack")
+    return stack
+
+
+def minmax_into_stack(img, stack, rho, N, precision="mixed", workspace=None, stream=None):
+    """abf_minmax writing alpha/beta into planes 0 and 1 of a stack buffer."""
+    img = _plane(img, "img")
+    h, w = img.shape
+    p = _prec(precision)
+    L = lib()
+    if stack.numel() < L.abf_stack_bytes(h, w, N, p):
+        raise ABFError("stack buffer too small")
+    if workspace is None:
+        workspace = _alloc_bytes(L.abf_scratch_bytes(h, w, rho), img.device)
+    a = ctypes.c_void_p(stack.data_ptr())
+    b = ctypes.c_void_p(stack.data_ptr() + int(L.abf_stack_plane_offset(h, w, N, p, 1)))
+    st = L.abf_minmax(_ptr(img), h, w, img.stride(0), int(rho), a, b, L.abf_stack_pitch(w),
+                      _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(st, "abf_minmax")
+    return stack
+
+
+def stack_moments(img, stack, kernel="box", rho=3, N=5, sigma_s=0.0, precision="mixed",
+                  stream=None):
+    """abf_stack_moments: moment planes of a stack whose bounds are present."""
+    img = _plane(img, "img")
+    h, w = img.shape
+    st = lib().abf_stack_moments(_ptr(img), h, w, img.stride(0), _kind(kernel), float(sigma_s),
+                                 int(rho), int(N), _prec(precision), _ptr(stack), stack.numel(),
+                                 _stream(stream))
+    _check(st, "abf_stack_moments")
+    return stack
+
+
+def stack_planes(stack, h, w, N, precision="mixed"):
+    """Views (alpha, beta, [a~_1..a~_N]) into a stack buffer, each (h, w)."""
+    torch = _torch()
+    p = _prec(precision)
+    L = lib()
+    P = int(L.abf_stack_pitch(w))
+
+    def view(plane, dtype):
+        off = int(L.abf_stack_plane_offset(h, w, N, p, plane))
+        esz = torch.tensor([], dtype=dtype).element_size()
+        flat = stack[off: off + P * h * esz].view(dtype)
+        return flat.view(h, P)[:, :w]
+
+    mdt = torch.float64 if p == 0 else torch.float32
+    return view(0, torch.float32), view(1, torch.float32), [view(2 + k, mdt) for k in range(N)]
+
+
+def range_from_stack(stack, sigma, img=None, theta=None, N=5, precision="mixed", clamp=True,
+                     out=None, stream=None):
+    """abf_range: the range stage from a moment stack built for the same image."""
+    torch = _torch()
+    sigma, img, theta = _plane(sigma, "sigma"), _plane(img, "img"), _plane(theta, "theta")
+    h, w = sigma.shape
+    ref = theta if theta is not None else img
+    if ref is None:
+        raise ABFError("either theta or img is required")
+    pitch = _common_pitch(sigma, img, theta)
+    p = _prec(precision)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=sigma.device)
+    st = lib().abf_range(_ptr(stack), stack.numel(), _ptr(img), _ptr(theta), _ptr(sigma), h, w,
+                         pitch, int(N), p, FLAG_CLAMP if clamp else 0, _ptr(out), out.stride(0),
+                         _stream(stream))
+    _check(st, "abf_range")
+    return out
+
+
+def fast_batched(items, precision="mixed", clamp=True, workspace=None, stream=None):
+    """abf_fast_batched. ``items``: list of dicts with keys img, sigma, theta
+    (optional), kernel, rho, N, sigma_s (optional), out (optional).
+    Returns the list of outputs."""
+    torch = _torch()
+    p = _prec(precision)
+    reqs = (Request * max(1, len(items)))()
+    outs = []
+    for i, it in enumerate(items):
+        img, sg, th = _plane(it["img"], "img"), _plane(it["sigma"], "sigma"), _plane(it.get("theta"), "theta")
+        h, w = img.shape
+        pitch = _common_pitch(img, sg, th)
+        out = it.get("out")
+        if out is None:
+            out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+        outs.append(out)
+        reqs[i] = Request(img.data_ptr(), th.data_ptr() if th is not None else None, sg.data_ptr(),
+                          h, w, pitch, _kind(it.get("kernel", "box")), float(it.get("sigma_s", 0.0)),
+                          int(it["rho"]), int(it["N"]), out.data_ptr(), out.stride(0))
+    need = lib().abf_batched_workspace_bytes(reqs, len(items), p)
+    if workspace is None and items:
+        workspace = _alloc_bytes(need, items[0]["img"].device)
+    st = lib().abf_fast_batched(reqs, len(items), p, FLAG_CLAMP if clamp else 0,
+                                _ptr(workspace) if workspace is not None else None,
+                                workspace.numel() if workspace is not None else 0, _stream(stream))
+    _check(st, "abf_fast_batched")
+    return outs

@@ -1,0 +1,82 @@
+// Internal declarations shared by the HIP translation units of libabf.
+// Device helpers, compile-time coefficient tables and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace abf {
+
+constexpr int kNMax = 8;
+constexpr int kRhoMax = 96;
+constexpr int kWave = 64;
+
+// Gauss-Legendre rule on [0, 1] used by the range kernel for small lambda.
+constexpr int kGLNodes = 16;
+struct GLRule {
+  double t[kGLNodes];
+  double w[kGLNodes];
+};
+// Computed once on the host (Newton iteration on P_Q), see api.cpp.
+const GLRule& gl_rule();
+
+// Coefficients of the Legendre polynomial P_k(z) = sum_r L[k][r] z^r
+// (three-term recurrence (k+1) P_{k+1} = (2k+1) z P_k - k P_{k-1}).
+struct LegTable {
+  double L[kNMax + 2][kNMax + 2];
+  constexpr LegTable() : L{} {
+    L[0][0] = 1.0;
+    L[1][1] = 1.0;
+    for (int k = 1; k <= kNMax; ++k)
+      for (int r = 0; r <= k + 1; ++r) {
+        double v = 0.0;
+        if (r >= 1) v += (2.0 * k + 1.0) * L[k][r - 1];
+        v -= k * L[k - 1][r];
+        L[k + 1][r] = v / (k + 1.0);
+      }
+  }
+};
+
+// Coefficients of the shifted Legendre polynomial P_k(2t - 1) in powers of
+// t: ell[k][r] = (-1)^(k+r) C(k, r) C(k+r, r) (integers, exact in FP64).
+struct ShiftedLegTable {
+  double ell[kNMax + 1][kNMax + 1];
+  constexpr ShiftedLegTable() : ell{} {
+    for (int k = 0; k <= kNMax; ++k)
+      for (int r = 0; r <= k; ++r) {
+        double c1 = 1.0, c2 = 1.0;  // C(k, r), C(k+r, r)
+        for (int i = 1; i <= r; ++i) {
+          c1 = c1 * (k - r + i) / i;
+          c2 = c2 * (k + i) / i;
+        }
+        ell[k][r] = (((k + r) & 1) ? -1.0 : 1.0) * c1 * c2;
+      }
+  }
+};
+
+// Launchers (all asynchronous on `stream`; return hipGetLastError()).
+hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rho,
+                         float* alpha, float* beta, long long out_pitch,
+                         void* scratch, hipStream_t stream);
+
+// prec: 0 = FP64 stack, 1 = FP32 stack. N >= 1. The alpha/beta planes of the
+// stack must already hold the window bounds.
+hipError_t launch_moments(const float* img, long long pitch, int h, int w,
+                          int kernel_kind, double sigma_s, int rho, int N, int prec,
+                          const float* alpha, const float* beta, long long sp,
+                          void* mom, long long plane_elems, hipStream_t stream);
+
+hipError_t launch_range(const float* alpha, const float* beta, long long sp,
+                        const void* mom, long long plane_elems,
+                        const float* theta_or_img, long long tpitch,
+                        const float* sigma, long long spitch, int h, int w,
+                        int N, int prec, unsigned flags, void* out, long long opitch,
+                        hipStream_t stream);
+
+hipError_t launch_brute(const float* img, const float* theta, const float* sigma,
+                        long long pitch, int h, int w, int kernel_kind, double sigma_s,
+                        int rho, int prec, void* out, long long opitch,
+                        hipStream_t stream);
+
+}  // namespace abf

@@ -1,0 +1,248 @@
+// C ABI of libabf: argument validation, workspace layout and dispatch to the
+// HIP kernels (see include/abf.h for the contract of every entry point).
+#include "../../include/abf.h"
+
+#include <cmath>
+#include <cstdint>
+#include <mutex>
+
+#include "abf_internal.h"
+
+namespace abf {
+
+// Gauss-Legendre nodes/weights on [0,1]: roots of P_Q by Newton iteration
+// from the Chebyshev-like initial guess cos(pi (i + 3/4) / (Q + 1/2)).
+const GLRule& gl_rule() {
+  static GLRule rule;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int Q = kGLNodes;
+    for (int i = 0; i < Q; ++i) {
+      double z = std::cos(M_PI * (i + 0.75) / (Q + 0.5));
+      double dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= Q; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = Q * (z * p1 - p0) / (z * z - 1.0);
+        const double dz = p1 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-17) break;
+      }
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= Q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = Q * (z * p1 - p0) / (z * z - 1.0);
+      rule.t[i] = 0.5 * (1.0 - z);                 // map [-1,1] -> [0,1]
+      rule.w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // = (2/((1-z^2) P'^2)) / 2
+    }
+  });
+  return rule;
+}
+
+}  // namespace abf
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+bool shape_ok(int h, int w, long long pitch) { return h >= 1 && w >= 1 && pitch >= w; }
+
+abf_status hip_status(hipError_t e) { return e == hipSuccess ? ABF_OK : ABF_E_HIP; }
+
+size_t elem_bytes(int prec) { return prec == ABF_PREC_FP64 ? 8 : 4; }
+
+bool prec_ok(int p) { return p == ABF_PREC_FP64 || p == ABF_PREC_MIXED; }
+bool kind_ok(int k) { return k == ABF_KERNEL_BOX || k == ABF_KERNEL_GAUSSIAN; }
+
+}  // namespace
+
+extern "C" {
+
+const char* abf_status_string(int s) {
+  switch (s) {
+    case ABF_OK: return "ok";
+    case ABF_E_INVALID: return "invalid argument";
+    case ABF_E_NOMEM: return "out of memory";
+    case ABF_E_HIP: return "HIP runtime error";
+    case ABF_E_UNSUPPORTED: return "unsupported parameter (N or rho out of the built range)";
+    case ABF_E_WORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+int abf_version(void) { return 100; }
+
+long long abf_stack_pitch(int w) { return w < 1 ? 0 : ((long long)w + 63) / 64 * 64; }
+
+size_t abf_stack_plane_offset(int h, int w, int N, int precision, int plane) {
+  (void)N;
+  const size_t P = (size_t)abf_stack_pitch(w) * (size_t)(h < 0 ? 0 : h);
+  if (plane <= 0) return 0;
+  if (plane == 1) return P * 4;
+  return P * 8 + (size_t)(plane - 2) * P * elem_bytes(precision);
+}
+
+size_t abf_stack_bytes(int h, int w, int N, int precision) {
+  if (h < 1 || w < 1 || N < 0) return 0;
+  return align_up(abf_stack_plane_offset(h, w, N, precision, N + 2));
+}
+
+size_t abf_scratch_bytes(int h, int w, int rho) {
+  (void)rho;
+  if (h < 1 || w < 1) return 0;
+  // transposed (min, max) intermediate of the separable window bounds
+  return align_up((size_t)w * (size_t)(((long long)h + 63) / 64 * 64) * 8);
+}
+
+size_t abf_workspace_bytes(int h, int w, int rho, int N, int precision) {
+  if (h < 1 || w < 1 || N < 0) return 0;
+  return abf_stack_bytes(h, w, N, precision) + abf_scratch_bytes(h, w, rho);
+}
+
+abf_status abf_minmax(const float* img, int h, int w, long long pitch, int rho, float* alpha,
+                      float* beta, long long out_pitch, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  if (!img || !alpha || !beta || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0)
+    return ABF_E_INVALID;
+  if (rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (!workspace || !aligned(workspace) || workspace_bytes < abf_scratch_bytes(h, w, rho))
+    return ABF_E_WORKSPACE;
+  return hip_status(abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, out_pitch, workspace,
+                                       static_cast<hipStream_t>(stream)));
+}
+
+abf_status abf_stack_moments(const float* img, int h, int w, long long pitch, int kernel_kind,
+                             double sigma_s, int rho, int N, int precision, void* stack,
+                             size_t stack_bytes, void* stream) {
+  if (!img || !stack || !shape_ok(h, w, pitch) || rho < 0 || N < 0 || !prec_ok(precision) ||
+      !kind_ok(kernel_kind) || !std::isfinite(sigma_s))
+    return ABF_E_INVALID;
+  if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (!aligned(stack) || stack_bytes < abf_stack_bytes(h, w, N, precision)) return ABF_E_WORKSPACE;
+  if (N == 0) return ABF_OK;
+  const long long sp = abf_stack_pitch(w);
+  char* base = static_cast<char*>(stack);
+  const float* alpha = reinterpret_cast<const float*>(base);
+  const float* beta = reinterpret_cast<const float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
+  void* mom = base + abf_stack_plane_offset(h, w, N, precision, 2);
+  return hip_status(abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N,
+                                        precision == ABF_PREC_FP64 ? 0 : 1, alpha, beta, sp, mom,
+                                        sp * h, static_cast<hipStream_t>(stream)));
+}
+
+abf_status abf_moment_stack(const float* img, int h, int w, long long pitch, int kernel_kind,
+                            double sigma_s, int rho, int N, int precision, void* stack,
+                            size_t stack_bytes, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  if (!img || !stack || !shape_ok(h, w, pitch) || rho < 0 || N < 0 || !prec_ok(precision) ||
+      !kind_ok(kernel_kind) || !std::isfinite(sigma_s))
+    return ABF_E_INVALID;
+  if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (!aligned(stack) || stack_bytes < abf_stack_bytes(h, w, N, precision)) return ABF_E_WORKSPACE;
+  if (!workspace || !aligned(workspace) || workspace_bytes < abf_scratch_bytes(h, w, rho))
+    return ABF_E_WORKSPACE;
+  const long long sp = abf_stack_pitch(w);
+  char* base = static_cast<char*>(stack);
+  float* alpha = reinterpret_cast<float*>(base);
+  float* beta = reinterpret_cast<float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
+  abf_status st = abf_minmax(img, h, w, pitch, rho, alpha, beta, sp, workspace, workspace_bytes,
+                             stream);
+  if (st != ABF_OK) return st;
+  return abf_stack_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N, precision, stack,
+                           stack_bytes, stream);
+}
+
+abf_status abf_range(const void* stack, size_t stack_bytes, const float* img, const float* theta,
+                     const float* sigma, int h, int w, long long pitch, int N, int precision,
+                     unsigned flags, void* out, long long out_pitch, void* stream) {
+  if (!stack || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || N < 0 ||
+      !prec_ok(precision) || (!theta && !img))
+    return ABF_E_INVALID;
+  if (N > ABF_N_MAX) return ABF_E_UNSUPPORTED;
+  if (!aligned(stack) || stack_bytes < abf_stack_bytes(h, w, N, precision)) return ABF_E_WORKSPACE;
+  const long long sp = abf_stack_pitch(w);
+  const char* base = static_cast<const char*>(stack);
+  const float* alpha = reinterpret_cast<const float*>(base);
+  const float* beta = reinterpret_cast<const float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
+  const void* mom = base + abf_stack_plane_offset(h, w, N, precision, 2);
+  return hip_status(abf::launch_range(alpha, beta, sp, mom, sp * h, theta ? theta : img, pitch,
+                                      sigma, pitch, h, w, N, precision == ABF_PREC_FP64 ? 0 : 1,
+                                      flags, out, out_pitch, static_cast<hipStream_t>(stream)));
+}
+
+abf_status abf_fast(const float* img, const float* theta, const float* sigma, int h, int w,
+                    long long pitch, int kernel_kind, double sigma_s, int rho, int N,
+                    int precision, unsigned flags, void* out, long long out_pitch,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (!img || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0 || N < 0 ||
+      !prec_ok(precision) || !kind_ok(kernel_kind))
+    return ABF_E_INVALID;
+  if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (!workspace || !aligned(workspace) ||
+      workspace_bytes < abf_workspace_bytes(h, w, rho, N, precision))
+    return ABF_E_WORKSPACE;
+  const size_t sb = abf_stack_bytes(h, w, N, precision);
+  char* ws = static_cast<char*>(workspace);
+  abf_status st = abf_moment_stack(img, h, w, pitch, kernel_kind, sigma_s, rho, N, precision, ws,
+                                   sb, ws + sb, workspace_bytes - sb, stream);
+  if (st != ABF_OK) return st;
+  return abf_range(ws, sb, img, theta, sigma, h, w, pitch, N, precision, flags, out, out_pitch,
+                   stream);
+}
+
+abf_status abf_bruteforce(const float* img, const float* theta, const float* sigma, int h, int w,
+                          long long pitch, int kernel_kind, double sigma_s, int rho,
+                          int precision, void* out, long long out_pitch, void* stream) {
+  if (!img || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0 ||
+      !prec_ok(precision) || !kind_ok(kernel_kind))
+    return ABF_E_INVALID;
+  if (rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  return hip_status(abf::launch_brute(img, theta, sigma, pitch, h, w, kernel_kind, sigma_s, rho,
+                                      precision == ABF_PREC_FP64 ? 0 : 1, out, out_pitch,
+                                      static_cast<hipStream_t>(stream)));
+}
+
+size_t abf_batched_workspace_bytes(const abf_request* reqs, int n, int precision) {
+  if (!reqs || n < 0) return 0;
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i)
+    tot += align_up(abf_workspace_bytes(reqs[i].h, reqs[i].w, reqs[i].rho, reqs[i].N, precision));
+  return tot;
+}
+
+abf_status abf_fast_batched(const abf_request* reqs, int n, int precision, unsigned flags,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  if (!reqs || n < 0 || !prec_ok(precision)) return ABF_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    const abf_request& r = reqs[i];
+    if (!r.img || !r.sigma || !r.out || !shape_ok(r.h, r.w, r.pitch) || r.out_pitch < r.w ||
+        r.rho < 0 || r.N < 0 || !kind_ok(r.kernel_kind))
+      return ABF_E_INVALID;
+    if (r.N > ABF_N_MAX || r.rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  }
+  if (n > 0 && (!workspace || !aligned(workspace) ||
+                workspace_bytes < abf_batched_workspace_bytes(reqs, n, precision)))
+    return ABF_E_WORKSPACE;
+  char* ws = static_cast<char*>(workspace);
+  for (int i = 0; i < n; ++i) {
+    const abf_request& r = reqs[i];
+    const size_t need = align_up(abf_workspace_bytes(r.h, r.w, r.rho, r.N, precision));
+    abf_status st = abf_fast(r.img, r.theta, r.sigma, r.h, r.w, r.pitch, r.kernel_kind, r.sigma_s,
+                             r.rho, r.N, precision, flags, r.out, r.out_pitch, ws, need, stream);
+    if (st != ABF_OK) return st;
+    ws += need;
+  }
+  return ABF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Window bounds alpha_i, beta_i (eq. bounds; Algorithm 1, line 2; Prop. 1).
+//
+// The min (max) over the (2R+1)^2 clamp-to-edge window is separable: a
+// 1-D sliding min along rows followed by a 1-D sliding min along columns.
+// Each 1-D pass uses the van Herk / Gil-Werman scheme, O(1) comparisons per
+// pixel for any R: split the padded row into blocks of w = 2R+1; the
+// window [x, x+2R] is the tail of one block plus the head of the next, so
+//     min = min(suffix_min(x), prefix_min(x + 2R)).
+//
+// One kernel does a row pass and writes its result TRANSPOSED, so the
+// column pass is the same row kernel run on the transposed intermediate
+// (both passes read and write rows, coalesced). A workgroup stages
+// ROWS padded rows in LDS; phase 1 writes the block suffixes into the
+// result tile, phase 2 folds in the block prefixes, phase 3 writes the
+// tile transposed. min and max are carried together as a float2.
+#include "abf_internal.h"
+
+namespace abf {
+namespace {
+
+constexpr int kTX = 64;        // output columns per workgroup
+constexpr int kThreads = 256;
+
+template <bool FIRST>
+__global__ __launch_bounds__(kThreads) void vh_rows(
+    const void* __restrict__ in, long long in_pitch, int rows, int cols, int R, int ROWS,
+    float2* __restrict__ out_t, long long out_pitch,   // FIRST: transposed float2
+    float* __restrict__ out_a, float* __restrict__ out_b, long long ab_pitch) {
+  extern __shared__ float2 smem[];
+  const int E = kTX + 2 * R;
+  float2* ext = smem;                 // ROWS x E
+  float2* res = smem + ROWS * E;      // ROWS x kTX
+  const int row0 = blockIdx.y * ROWS;
+  const int col0 = blockIdx.x * kTX;
+
+  for (int i = threadIdx.x; i < ROWS * E; i += kThreads) {
+    const int r = i / E, e = i - r * E;
+    const int gr = min(row0 + r, rows - 1);
+    const int gc = min(max(col0 - R + e, 0), cols - 1);
+    float2 v;
+    if (FIRST) {
+      const float f = static_cast<const float*>(in)[(long long)gr * in_pitch + gc] + 0.0f;
+      v = make_float2(f, f);
+    } else {
+      v = static_cast<const float2*>(in)[(long long)gr * in_pitch + gc];
+    }
+    ext[i] = v;
+  }
+  __syncthreads();
+
+  const int w = 2 * R + 1;
+  const int nb = (E + w - 1) / w;
+  // phase 1: block suffixes, needed at e in [0, kTX)
+  const int nb1 = min(nb, (kTX + w - 1) / w);
+  for (int it = threadIdx.x; it < ROWS * nb1; it += kThreads) {
+    const int r = it % ROWS, b = it / ROWS;
+    const int s = b * w, e_end = min(s + w, E);
+    float mn = INFINITY, mx = -INFINITY;
+    const float2* er = ext + r * E;
+    for (int e = e_end - 1; e >= s; --e) {
+      const float2 v = er[e];
+      mn = fminf(mn, v.x);
+      mx = fmaxf(mx, v.y);
+      if (e < kTX) res[r * kTX + e] = make_float2(mn, mx);
+    }
+  }
+  __syncthreads();
+  // phase 2: block prefixes, needed at e in [2R, 2R + kTX)
+  const int b0 = (2 * R) / w;
+  const int nb2 = nb - b0;
+  for (int it = threadIdx.x; it < ROWS * nb2; it += kThreads) {
+    const int r = it % ROWS, b = b0 + it / ROWS;
+    const int s = b * w, e_end = min(s + w, E);
+    float mn = INFINITY, mx = -INFINITY;
+    const float2* er = ext + r * E;
+    for (int e = s; e < e_end; ++e) {
+      const float2 v = er[e];
+      mn = fminf(mn, v.x);
+      mx = fmaxf(mx, v.y);
+      if (e >= 2 * R) {
+        float2* o = res + r * kTX + (e - 2 * R);
+        const float2 p = *o;
+        *o = make_float2(fminf(p.x, mn), fmaxf(p.y, mx));
+      }
+    }
+  }
+  __syncthreads();
+  // phase 3: transposed store; consecutive threads take consecutive rows so
+  // each output row (an input column) is written contiguously.
+  for (int i = threadIdx.x; i < ROWS * kTX; i += kThreads) {
+    const int r = i % ROWS, x = i / ROWS;
+    const int gr = row0 + r, gc = col0 + x;
+    if (gr < rows && gc < cols) {
+      const float2 v = res[r * kTX + x];
+      if (FIRST) {
+        out_t[(long long)gc * out_pitch + gr] = v;
+      } else {
+        out_a[(long long)gc * ab_pitch + gr] = v.x;
+        out_b[(long long)gc * ab_pitch + gr] = v.y;
+      }
+    }
+  }
+}
+
+int rows_per_block(int R) {
+  // keep the LDS footprint ROWS * (2*kTX + 2R) * 8 bytes within 64 KiB
+  int rows = 64;
+  while (rows > 1 && (size_t)rows * (2 * kTX + 2 * R) * 8 > 65536) rows >>= 1;
+  return rows;
+}
+
+}  // namespace
+
+hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rho,
+                         float* alpha, float* beta, long long out_pitch,
+                         void* scratch, hipStream_t stream) {
+  // The window clipped to the image is the same for any radius >= dim - 1.
+  const int Rh = rho < w - 1 ? rho : w - 1;
+  const int Rv = rho < h - 1 ? rho : h - 1;
+  const long long tp = ((long long)h + 63) / 64 * 64;   // pitch of transposed rows
+  float2* t = static_cast<float2*>(scratch);
+  {
+    const int ROWS = rows_per_block(Rh);
+    dim3 grid((w + kTX - 1) / kTX, (h + ROWS - 1) / ROWS);
+    size_t lds = (size_t)ROWS * (2 * kTX + 2 * Rh) * sizeof(float2);
+    hipLaunchKernelGGL(vh_rows<true>, grid, dim3(kThreads), lds, stream,
+                       img, pitch, h, w, Rh, ROWS, t, tp, nullptr, nullptr, 0LL);
+  }
+  {
+    const int ROWS = rows_per_block(Rv);
+    dim3 grid((h + kTX - 1) / kTX, (w + ROWS - 1) / ROWS);
+    size_t lds = (size_t)ROWS * (2 * kTX + 2 * Rv) * sizeof(float2);
+    hipLaunchKernelGGL(vh_rows<false>, grid, dim3(kThreads), lds, stream,
+                       (const void*)t, tp, w, h, Rv, ROWS, nullptr, 0LL, alpha, beta, out_pitch);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace abf

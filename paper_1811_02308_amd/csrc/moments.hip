@@ -1,0 +1,334 @@
+// Moment stack: Algorithm 1 lines 6-9 (Props. 2 and 3), fused with the
+// change of basis to shifted-Legendre moments.
+//
+// For every pixel i the kernels form the window moments of the power images
+// (Prop. 2: sum_t t^k h_i(t) = (omega * f^k)(i)) and turn them into the
+// moments of the histogram stretched to [alpha_i, beta_i] (Prop. 3), kept as
+// a~_k = sum_j omega_j P_k(z_j), z_j = (f(i-j) - mid_i) / half_i in [-1, 1],
+// mid_i = (alpha_i + beta_i)/2, half_i = (beta_i - alpha_i)/2. This equals
+// sum_r ell_kr mu_r for the mu_r of eq. (hist_moments_new).
+//
+// Numerics. Power sums are FP64 and taken about a per-wave origin c (the
+// window mid-range at the centre of the wave's tile) instead of 0, which
+// shrinks the binomial shift's cancellation: its error grows like
+// ((|mid_i - c| + half_i) / half_i)^k times the rounding of the sums.
+//
+// Work decomposition (box kernel). One wave owns a strip of 256 padded
+// columns (4 consecutive columns per lane) and a segment of TH output rows.
+// It slides a vertical running sum down the segment (add the entering row,
+// subtract the leaving row: O(1) per pixel in R), then forms the
+// horizontal window sums from a wave-wide inclusive prefix of the vertical
+// sums held in LDS: sum over [x-R, x+R] = P(x+R) - P(x-R-1). Outputs are
+// the 256 - R - Rpad columns whose window lies inside the strip; strips
+// overlap by the halo. The per-pixel epilogue (shift, scale, Legendre)
+// reads the prefix from LDS with lanes mapped to consecutive output
+// columns, so alpha/beta loads and moment stores are coalesced.
+//
+// Gaussian kernel: same wave/strip layout; vertical and horizontal sums
+// are direct weighted sums (O(R) per pixel, weights in LDS).
+#include "abf_internal.h"
+
+namespace abf {
+namespace {
+
+constexpr int kV = 4;                    // columns per lane
+constexpr int kStrip = kWave * kV;       // padded columns per wave
+constexpr int kWaves = 4;                // waves per workgroup
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_inclusive_scan(double v, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double t = __shfl_up(v, off, kWave);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// Per-pixel epilogue: m[1..N] are the window moments of u = f - c (m[0] = 1).
+// Writes a~_1..a~_N (or zeros if alpha == beta).
+template <int N, typename TS>
+__device__ __forceinline__ void store_legendre(double (&m)[N + 1], float a, float b, double c,
+                                               TS* __restrict__ mom, long long plane,
+                                               long long idx) {
+  constexpr LegTable LT{};
+  if (a == b) {
+#pragma unroll
+    for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(0);
+    return;
+  }
+  const double mid = 0.5 * ((double)a + (double)b) - c;
+  const double half = 0.5 * ((double)b - (double)a);
+  // binomial shift of the moments to the origin mid (Prop. 3):
+  // nu_k = sum_r C(k, r) (-mid)^(k-r) m_r, by repeated synthetic steps
+  const double s = -mid;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int k = N; k > j; --k) m[k] = fma(s, m[k - 1], m[k]);
+  // scale to z in [-1, 1]
+  const double ih = 1.0 / half;
+  double sc = ih;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    m[k] *= sc;
+    sc *= ih;
+  }
+  // Legendre moments a~_k = sum_r L[k][r] nu_r (only r = k, k-2, ... are non-zero)
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = k; r >= 0; r -= 2) acc = fma(LT.L[k][r], m[r], acc);
+    mom[(k - 1) * plane + idx] = TS(acc);
+  }
+}
+
+struct StripGeom {
+  int O;       // output columns per strip
+  int Rpad;    // R rounded up to a multiple of kV
+  int TH;      // output rows per segment
+  int n_strips;
+  int n_segs;
+};
+
+template <int N, typename TS>
+__global__ __launch_bounds__(kWaves * kWave) void moments_box(
+    const float* __restrict__ img, long long pitch, int H, int W, int R,
+    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    TS* __restrict__ mom, long long plane, StripGeom g) {
+  __shared__ double sh[kWaves][N][kStrip];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int gw = blockIdx.x * kWaves + wv;
+  if (gw >= g.n_strips * g.n_segs) return;
+  const int strip = gw % g.n_strips;
+  const int seg = gw / g.n_strips;
+  const int y0 = seg * g.TH;
+  const int y1 = min(H, y0 + g.TH);
+  const int xo = strip * g.O;            // first output column of the strip
+  const int xs = xo - g.Rpad;            // padded column 0
+  const int xc = min(W - 1, xo + g.O / 2);
+  const int yc = min(H - 1, y0 + g.TH / 2);
+  const double c = 0.5 * ((double)alpha[(long long)yc * sp + xc] + (double)beta[(long long)yc * sp + xc]);
+
+  int cx[kV];
+#pragma unroll
+  for (int v = 0; v < kV; ++v) cx[v] = min(max(xs + kV * lane + v, 0), W - 1);
+
+  double S[N][kV];
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int v = 0; v < kV; ++v) S[k][v] = 0.0;
+
+  for (int dy = -R; dy <= R; ++dy) {
+    const float* row = img + (long long)min(max(y0 + dy, 0), H - 1) * pitch;
+#pragma unroll
+    for (int v = 0; v < kV; ++v) {
+      const double u = (double)row[cx[v]] - c;
+      double p = u;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        S[k][v] += p;
+        p *= u;
+      }
+    }
+  }
+
+  const double inv_area = 1.0 / ((double)(2 * R + 1) * (double)(2 * R + 1));
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0) {
+      const float* rin = img + (long long)min(y + R, H - 1) * pitch;
+      const float* rout = img + (long long)max(y - R - 1, 0) * pitch;
+#pragma unroll
+      for (int v = 0; v < kV; ++v) {
+        const double ui = (double)rin[cx[v]] - c;
+        const double uo = (double)rout[cx[v]] - c;
+        double pi = ui, po = uo;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          S[k][v] += pi - po;
+          pi *= ui;
+          po *= uo;
+        }
+      }
+    }
+    // horizontal: inclusive prefix of the vertical sums along the strip
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double p0 = S[k][0];
+      double p1 = p0 + S[k][1];
+      double p2 = p1 + S[k][2];
+      double p3 = p2 + S[k][3];
+      const double incl = wave_inclusive_scan(p3, lane);
+      const double ex = incl - p3;
+      double* d = &sh[wv][k][kV * lane];
+      d[0] = ex + p0;
+      d[1] = ex + p1;
+      d[2] = ex + p2;
+      d[3] = incl;
+    }
+    wave_sync();
+    for (int j = lane; j < g.O; j += kWave) {
+      const int x = xo + j;
+      if (x >= W) break;
+      const int e = g.Rpad + j;
+      double m[N + 1];
+      m[0] = 1.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double hi = sh[wv][k][e + R];
+        const double lo = (e - R - 1 >= 0) ? sh[wv][k][e - R - 1] : 0.0;
+        m[k + 1] = (hi - lo) * inv_area;
+      }
+      const long long idx = (long long)y * sp + x;
+      store_legendre<N, TS>(m, alpha[idx], beta[idx], c, mom, plane, idx);
+    }
+    wave_sync();
+  }
+}
+
+template <int N, typename TS>
+__global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
+    const float* __restrict__ img, long long pitch, int H, int W, int R, double inv2s2,
+    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    TS* __restrict__ mom, long long plane, StripGeom g) {
+  __shared__ double sh[kWaves][N][kStrip];
+  __shared__ double wts[2 * kRhoMax + 1];
+  for (int i = threadIdx.x; i <= 2 * R; i += blockDim.x) {
+    const double d = (double)(i - R);
+    wts[i] = exp(-d * d * inv2s2);
+  }
+  __syncthreads();
+  double z = 0.0;
+  for (int i = 0; i <= 2 * R; ++i) z += wts[i];
+  const double iz = 1.0 / z;       // 1-D normalisation (2-D weight = product)
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int gw = blockIdx.x * kWaves + wv;
+  if (gw >= g.n_strips * g.n_segs) return;
+  const int strip = gw % g.n_strips;
+  const int seg = gw / g.n_strips;
+  const int y0 = seg * g.TH;
+  const int y1 = min(H, y0 + g.TH);
+  const int xo = strip * g.O;
+  const int xs = xo - g.Rpad;
+  const int xc = min(W - 1, xo + g.O / 2);
+  const int yc = min(H - 1, y0 + g.TH / 2);
+  const double c = 0.5 * ((double)alpha[(long long)yc * sp + xc] + (double)beta[(long long)yc * sp + xc]);
+
+  int cx[kV];
+#pragma unroll
+  for (int v = 0; v < kV; ++v) cx[v] = min(max(xs + kV * lane + v, 0), W - 1);
+
+  for (int y = y0; y < y1; ++y) {
+    double S[N][kV];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int v = 0; v < kV; ++v) S[k][v] = 0.0;
+    for (int dy = -R; dy <= R; ++dy) {
+      const float* row = img + (long long)min(max(y + dy, 0), H - 1) * pitch;
+      const double wy = wts[dy + R] * iz;
+#pragma unroll
+      for (int v = 0; v < kV; ++v) {
+        const double u = (double)row[cx[v]] - c;
+        double p = u;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          S[k][v] = fma(wy, p, S[k][v]);
+          p *= u;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int v = 0; v < kV; ++v) sh[wv][k][kV * lane + v] = S[k][v];
+    wave_sync();
+    for (int j = lane; j < g.O; j += kWave) {
+      const int x = xo + j;
+      if (x >= W) break;
+      const int e = g.Rpad + j;
+      double m[N + 1];
+      m[0] = 1.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) m[k + 1] = 0.0;
+      for (int dx = -R; dx <= R; ++dx) {
+        const double wx = wts[dx + R] * iz;
+#pragma unroll
+        for (int k = 0; k < N; ++k) m[k + 1] = fma(wx, sh[wv][k][e + dx], m[k + 1]);
+      }
+      const long long idx = (long long)y * sp + x;
+      store_legendre<N, TS>(m, alpha[idx], beta[idx], c, mom, plane, idx);
+    }
+    wave_sync();
+  }
+}
+
+StripGeom make_geom(int H, int W, int R, int target_waves) {
+  StripGeom g;
+  g.Rpad = (R + kV - 1) / kV * kV;
+  g.O = (kStrip - R - g.Rpad) / kV * kV;
+  g.n_strips = (W + g.O - 1) / g.O;
+  // rows per segment: long segments amortise the 2R-row warm-up of the
+  // running sums; short ones give enough waves to fill the device
+  int th = 64;
+  while (th > 8 && (long long)g.n_strips * ((H + th - 1) / th) < target_waves) th >>= 1;
+  g.TH = th;
+  g.n_segs = (H + th - 1) / th;
+  return g;
+}
+
+template <int N, typename TS>
+hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int kind,
+                            double sigma_s, int R, const float* alpha, const float* beta,
+                            long long sp, TS* mom, long long plane, hipStream_t stream) {
+  const StripGeom g = make_geom(h, w, R, 4096);
+  const int waves = g.n_strips * g.n_segs;
+  dim3 grid((waves + kWaves - 1) / kWaves);
+  if (kind == 0) {
+    hipLaunchKernelGGL((moments_box<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
+                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g);
+  } else {
+    const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
+    hipLaunchKernelGGL((moments_gauss<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
+                       img, pitch, h, w, R, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, g);
+  }
+  return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, int kind,
+                      double sigma_s, int R, const float* alpha, const float* beta,
+                      long long sp, TS* mom, long long plane, hipStream_t stream) {
+  switch (N) {
+#define ABF_CASE(n) \
+  case n: return launch_moments_t<n, TS>(img, pitch, h, w, kind, sigma_s, R, alpha, beta, sp, mom, plane, stream);
+    ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6) ABF_CASE(7) ABF_CASE(8)
+#undef ABF_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_moments(const float* img, long long pitch, int h, int w,
+                          int kernel_kind, double sigma_s, int rho, int N, int prec,
+                          const float* alpha, const float* beta, long long sp,
+                          void* mom, long long plane_elems, hipStream_t stream) {
+  if (prec == 0)
+    return dispatch_n<double>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
+                              static_cast<double*>(mom), plane_elems, stream);
+  return dispatch_n<float>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
+                           static_cast<float*>(mom), plane_elems, stream);
+}
+
+}  // namespace abf

@@ -1,0 +1,191 @@
+// Range stage: Algorithm 1 lines 10-20 from the moment stack, one thread
+// per pixel, all arithmetic in FP64 registers.
+//
+//   p(t) = sum_k c_k t^k is the degree-N polynomial whose moments on [0,1]
+//   match those of the stretched histogram (eq. match); with the stored
+//   Legendre moments it is p(t) = sum_k (2k+1) a~_k P_k(2t-1), and its
+//   monomial coefficients are c = A^-1 mu = sum_k (2k+1) a~_k ell_k
+//   (eq. inv; A^-1 = sum_k (2k+1) ell_k ell_k^T exactly).
+//   t0 = (theta - alpha)/(beta - alpha), lambda = (beta-alpha)^2/(2 sigma^2)
+//   (eq. sub), T1 = int_0^1 t p psi, T2 = int_0^1 p psi with
+//   psi = exp(-lambda (t - t0)^2), and g^ = alpha + (beta-alpha) T1/T2
+//   (eq. BFfinal).
+//
+// Two evaluations of T1, T2, chosen per pixel by lambda:
+//   lambda >= kLamSplit: the paper's route. I_0 from two error functions
+//     (eq. I_0), I_1 (eq. I_1), I_2..I_{N+1} by the integration-by-parts
+//     recursion (eq. F_forward), T1 = sum c_k I_{k+1}, T2 = sum c_k I_k.
+//     Every I_k is scaled by exp(lambda d^2), d = dist(t0, [0,1]), so that
+//     theta far outside [alpha, beta] cannot underflow; with that scaling
+//     the erf difference is written with erfcx (scaled complementary error
+//     function), which has no cancellation when both arguments share a
+//     sign. The common factor cancels in T1/T2.
+//   lambda < kLamSplit: the recursion divides by 2 lambda and loses
+//     accuracy as lambda -> 0, so T1 and T2 are integrated directly with a
+//     16-node Gauss-Legendre rule on [0,1], p evaluated by the Clenshaw
+//     recurrence in the Legendre basis (no monomial cancellation).
+// Post-rules: if T2 <= 0 or T1/T2 is not finite, F = I_1/I_0 (the N = 0
+// estimate); ABF_FLAG_CLAMP clips F to [0,1]. alpha == beta gives f(i).
+#include "abf_internal.h"
+
+namespace abf {
+namespace {
+
+constexpr double kLamSplit = 4.0;
+constexpr double kSqrtPi = 1.7724538509055160273;
+
+struct GLArgs {
+  double t[kGLNodes];
+  double w[kGLNodes];
+};
+
+template <int N, typename TS, typename TO>
+__global__ __launch_bounds__(256) void range_kernel(
+    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    const TS* __restrict__ mom, long long plane, const float* __restrict__ theta,
+    long long tpitch, const float* __restrict__ sigma, long long spitch, int H, int W,
+    unsigned flags, TO* __restrict__ out, long long opitch, GLArgs gl) {
+  constexpr ShiftedLegTable SL{};
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  const long long idx = (long long)y * sp + x;
+  const float a = alpha[idx], b = beta[idx];
+  TO* o = out + (long long)y * opitch + x;
+  if (a == b) {
+    *o = TO(a);
+    return;
+  }
+  const double da = a, delta = (double)b - da;
+  const double th = theta[(long long)y * tpitch + x];
+  const double sg = sigma[(long long)y * spitch + x];
+  const double t0 = (th - da) / delta;
+  const double lam = delta * delta / (2.0 * sg * sg);
+
+  double ak[N + 1];                      // (2k+1) a~_k
+  ak[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) ak[k] = (2.0 * k + 1.0) * (double)mom[(k - 1) * plane + idx];
+
+  double T1, T2, F0;
+  if (lam >= kLamSplit) {
+    double c[N + 1];
+#pragma unroll
+    for (int r = 0; r <= N; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = r; k <= N; ++k) acc = fma(ak[k], SL.ell[k][r], acc);
+      c[r] = acc;
+    }
+    const double sl = sqrt(lam);
+    const double A = -sl * t0, B = sl * (1.0 - t0);
+    const double ts = fmin(fmax(t0, 0.0), 1.0);
+    const double dd = t0 - ts;
+    const double s = lam * dd * dd;
+    const double E0 = exp(s - A * A);    // exp(-lam t0^2) * e^s
+    const double E1 = exp(s - B * B);    // exp(-lam (1-t0)^2) * e^s
+    double diff;                          // (erf(B) - erf(A)) * e^s
+    if (A <= 0.0 && B >= 0.0) {
+      diff = 2.0 - erfcx(B) * E1 - erfcx(-A) * E0;
+    } else if (A > 0.0) {
+      diff = erfcx(A) * E0 - erfcx(B) * E1;
+    } else {
+      diff = erfcx(-B) * E1 - erfcx(-A) * E0;
+    }
+    const double i2l = 0.5 / lam;
+    double Im2 = 0.5 * kSqrtPi / sl * diff;          // I_0
+    double Im1 = fma(t0, Im2, (E0 - E1) * i2l);      // I_1
+    F0 = Im1 / Im2;
+    T2 = c[0] * Im2;
+    T1 = c[0] * Im1;
+    const double e1l = E1 * i2l;
+#pragma unroll
+    for (int k = 2; k <= N + 1; ++k) {
+      const double Ik = fma(t0, Im1, fma((k - 1) * i2l, Im2, -e1l));
+      T1 = fma(c[k - 1], Ik, T1);
+      T2 = fma(c[k - 1], Im1, T2);
+      Im2 = Im1;
+      Im1 = Ik;
+    }
+  } else {
+    const double ts = fmin(fmax(t0, 0.0), 1.0);
+    T1 = T2 = 0.0;
+    double J0 = 0.0, J1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGLNodes; ++q) {
+      const double t = gl.t[q];
+      const double z = 2.0 * t - 1.0;
+      // Clenshaw: p = sum_k ak[k] P_k(z)
+      double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+      for (int k = N; k >= 0; --k) {
+        const double bk = ak[k] + ((2.0 * k + 1.0) / (k + 1.0)) * z * b1 - ((k + 1.0) / (k + 2.0)) * b2;
+        b2 = b1;
+        b1 = bk;
+      }
+      const double wpsi = gl.w[q] * exp(-lam * (t - ts) * (t + ts - 2.0 * t0));
+      J0 += wpsi;
+      J1 = fma(wpsi, t, J1);
+      T2 = fma(wpsi, b1, T2);
+      T1 = fma(wpsi * t, b1, T1);
+    }
+    F0 = J1 / J0;
+  }
+  double F = T1 / T2;
+  if (!(T2 > 0.0) || !isfinite(F)) F = F0;
+  if (flags & 1u) F = fmin(fmax(F, 0.0), 1.0);
+  *o = TO(fma(delta, F, da));
+}
+
+template <int N, typename TS, typename TO>
+hipError_t launch_t(const float* alpha, const float* beta, long long sp, const void* mom,
+                    long long plane, const float* theta, long long tpitch, const float* sigma,
+                    long long spitch, int h, int w, unsigned flags, void* out, long long opitch,
+                    hipStream_t stream) {
+  GLArgs gl;
+  const GLRule& r = gl_rule();
+  for (int q = 0; q < kGLNodes; ++q) {
+    gl.t[q] = r.t[q];
+    gl.w[q] = r.w[q];
+  }
+  dim3 grid((w + 63) / 64, (h + 3) / 4);
+  hipLaunchKernelGGL((range_kernel<N, TS, TO>), grid, dim3(256), 0, stream, alpha, beta, sp,
+                     static_cast<const TS*>(mom), plane, theta, tpitch, sigma, spitch, h, w,
+                     flags, static_cast<TO*>(out), opitch, gl);
+  return hipGetLastError();
+}
+
+template <typename TS, typename TO>
+hipError_t dispatch(int N, const float* alpha, const float* beta, long long sp, const void* mom,
+                    long long plane, const float* theta, long long tpitch, const float* sigma,
+                    long long spitch, int h, int w, unsigned flags, void* out, long long opitch,
+                    hipStream_t stream) {
+  switch (N) {
+#define ABF_CASE(n)                                                                           \
+  case n:                                                                                     \
+    return launch_t<n, TS, TO>(alpha, beta, sp, mom, plane, theta, tpitch, sigma, spitch, h, \
+                               w, flags, out, opitch, stream);
+    ABF_CASE(0) ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6)
+    ABF_CASE(7) ABF_CASE(8)
+#undef ABF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_range(const float* alpha, const float* beta, long long sp,
+                        const void* mom, long long plane_elems,
+                        const float* theta_or_img, long long tpitch,
+                        const float* sigma, long long spitch, int h, int w,
+                        int N, int prec, unsigned flags, void* out, long long opitch,
+                        hipStream_t stream) {
+  if (prec == 0)
+    return dispatch<double, double>(N, alpha, beta, sp, mom, plane_elems, theta_or_img, tpitch,
+                                    sigma, spitch, h, w, flags, out, opitch, stream);
+  return dispatch<float, float>(N, alpha, beta, sp, mom, plane_elems, theta_or_img, tpitch,
+                                sigma, spitch, h, w, flags, out, opitch, stream);
+}
+
+}  // namespace abf

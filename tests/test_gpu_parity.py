@@ -1,0 +1,254 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Bars: window bounds and passthrough pixels bit-exact; FP64 path within
+1e-6 and mixed path within 0.05 intensity units (on [0, 255]) of the
+oracle's fast filter; brute force within 1e-9 (FP64) / 2e-3 (FP32).
+Small images are compared at every pixel; full-size workloads at sampled
+pixels (corners, edges and a seeded random set) that the oracle evaluates
+one by one on the full image.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.spatial import window_minmax
+from synth import WORKLOADS, rect_scene, smooth_field, voronoi, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-6, "mixed": 0.05}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def abf():
+    import paper_1811_02308_amd as m
+    m.lib()          # fails loudly if the library is missing
+    return m
+
+
+def dev(torch, a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def sample_pixels(H, W, n=1500, seed=0):
+    rng = np.random.default_rng(seed)
+    ys = list(rng.integers(0, H, n)) + [0, 0, H - 1, H - 1, H // 2, 0, H - 1, H // 2]
+    xs = list(rng.integers(0, W, n)) + [0, W - 1, 0, W - 1, 0, W // 2, W // 2, W - 1]
+    return np.array(ys), np.array(xs)
+
+
+def run_fast(torch, abf, wl, precision, **kw):
+    out = abf.fast(dev(torch, wl["f"]), dev(torch, wl["sigma"]), theta=dev(torch, wl["theta"]),
+                   kernel=wl["kernel"], rho=wl["R"], N=wl["N"], sigma_s=wl["sigma_s"],
+                   precision=precision, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+# ----------------------------------------------------------------- bounds
+@pytest.mark.parametrize("shape,R", [((256, 256), 3), ((37, 300), 5), ((300, 37), 20), ((1, 129), 4),
+                                     ((129, 1), 4), ((5, 7), 20), ((1, 1), 3), ((70, 90), 0),
+                                     ((200, 333), 96)])
+def test_minmax_bit_exact(torch, abf, shape, R):
+    f = rect_scene(11, *shape, n_rect=4, noise=10, side_lo=1, side_hi=max(2, min(shape)))
+    a, b = abf.minmax(dev(torch, f), R)
+    torch.cuda.synchronize()
+    lo, hi = window_minmax(f, R)
+    assert np.array_equal(a.cpu().numpy(), lo)
+    assert np.array_equal(b.cpu().numpy(), hi)
+
+
+def test_minmax_voronoi_full(torch, abf):
+    f = voronoi(1003, 1024, 1536, n_seed=64)
+    for R in (5, 20):
+        a, b = abf.minmax(dev(torch, f), R)
+        torch.cuda.synchronize()
+        lo, hi = window_minmax(f, R)
+        assert np.array_equal(a.cpu().numpy(), lo) and np.array_equal(b.cpu().numpy(), hi)
+
+
+# ----------------------------------------------------------------- stack
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kernel,R,N", [("box", 3, 5), ("box", 20, 8), ("gaussian", 6, 6)])
+def test_moment_stack_matches_oracle(torch, abf, precision, kernel, R, N):
+    f = rect_scene(21, 96, 280, n_rect=6, noise=10, side_lo=8, side_hi=64)
+    st = abf.moment_stack(dev(torch, f), kernel=kernel, rho=R, N=N, precision=precision)
+    torch.cuda.synchronize()
+    a, b, mom = abf.stack_planes(st, *f.shape, N, precision)
+    _, aux = oracle.fast_abf(f, None, np.full(f.shape, 20.0), kernel, R, N, aux=True)
+    assert np.array_equal(a.cpu().numpy(), aux["alpha"].astype(np.float32))
+    assert np.array_equal(b.cpu().numpy(), aux["beta"].astype(np.float32))
+    live = aux["alpha"] != aux["beta"]
+    tol = 1e-8 if precision == "fp64" else 2e-6
+    for k in range(N):
+        got = mom[k].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got[live] - aux["amom"][..., k + 1][live])) < tol, k
+        assert np.all(got[~live] == 0)
+
+
+# ----------------------------------------------------------------- range alone
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_range_stage_on_oracle_stack(torch, abf, precision):
+    """Feed the oracle's own bounds and Legendre moments to abf_range, which
+    isolates the range kernel's error (integrals, fit, ratio)."""
+    f = rect_scene(5, 64, 200, n_rect=5, noise=10, side_lo=8, side_hi=40)
+    zeta = smooth_field(np.random.default_rng(3), *f.shape, -20, 20)
+    th = (f + zeta).astype(np.float32)
+    sg = smooth_field(np.random.default_rng(4), *f.shape, 3, 90)
+    sg[:8, :8] = np.inf
+    N, R = 8, 4
+    ref, aux = oracle.fast_abf(f, th, sg, "box", R, N, aux=True)
+    st = abf.moment_stack(dev(torch, f), kernel="box", rho=R, N=N, precision=precision)
+    a, b, mom = abf.stack_planes(st, *f.shape, N, precision)
+    mdt = torch.float64 if precision == "fp64" else torch.float32
+    for k in range(N):
+        mom[k].copy_(torch.from_numpy(np.nan_to_num(aux["amom"][..., k + 1]) * (aux["alpha"] != aux["beta"])).to(mdt))
+    out = abf.range_from_stack(st, dev(torch, sg), img=dev(torch, f), theta=dev(torch, th), N=N,
+                               precision=precision)
+    torch.cuda.synchronize()
+    err = np.abs(out.cpu().numpy().astype(np.float64) - ref)
+    assert np.max(err) < (2e-7 if precision == "fp64" else 1e-3), np.max(err)
+
+
+# ----------------------------------------------------------------- end to end
+SMALL = [("box", 3, 5), ("box", 1, 0), ("box", 2, 1), ("box", 5, 8), ("gaussian", 4, 6), ("gaussian", 9, 3)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kernel,R,N", SMALL)
+def test_fast_small_images_every_pixel(torch, abf, precision, kernel, R, N):
+    f = rect_scene(7 + R, 72, 301, n_rect=6, noise=10, side_lo=6, side_hi=48)
+    sg = smooth_field(np.random.default_rng(R), *f.shape, 10, 30)
+    wl = dict(f=f, theta=None, sigma=sg, kernel=kernel, R=R, N=N, sigma_s=0.0)
+    got = run_fast(torch, abf, wl, precision)
+    ref = oracle.fast_abf(f, None, sg, kernel, R, N)
+    lo, hi = window_minmax(f, R)
+    flat = lo == hi
+    assert np.array_equal(got[flat], f[flat].astype(np.float64))
+    assert np.max(np.abs(got - ref)) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fast_rects256_full(torch, abf, precision):
+    wl = workload("rects256_box3_n5")
+    got = run_fast(torch, abf, wl, precision)
+    ref = oracle.fast_abf(wl["f"], wl["theta"], wl["sigma"], wl["kernel"], wl["R"], wl["N"])
+    assert np.max(np.abs(got - ref)) < TOL[precision]
+
+
+@pytest.fixture(scope="module")
+def sharpen():
+    return workload("sharpen1024_gauss15_n6")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fast_sharpen1024_sampled(torch, abf, sharpen, precision):
+    wl = sharpen
+    got = run_fast(torch, abf, wl, precision)
+    ys, xs = sample_pixels(*wl["f"].shape, n=1500, seed=2)
+    ref = oracle.fast_abf(wl["f"], wl["theta"], wl["sigma"], wl["kernel"], wl["R"], wl["N"],
+                          sigma_s=wl["sigma_s"], pixels=(ys, xs))
+    assert np.max(np.abs(got[ys, xs] - ref)) < TOL[precision]
+
+
+@pytest.fixture(scope="module")
+def vor4096():
+    return voronoi(1003, 4096, 4096)
+
+
+@pytest.mark.parametrize("R", [5, 20])
+@pytest.mark.parametrize("N", [5, 8])
+def test_fast_voronoi4096_sampled(torch, abf, vor4096, R, N):
+    wl = WORKLOADS[f"voronoi4096_box{R}_n{N}"]()
+    assert np.array_equal(wl["f"], vor4096)
+    ys, xs = sample_pixels(4096, 4096, n=800, seed=R + N)
+    ref = oracle.fast_abf(wl["f"], None, wl["sigma"], "box", R, N, pixels=(ys, xs))
+    for precision in ("fp64", "mixed"):
+        got = run_fast(torch, abf, wl, precision)
+        assert np.max(np.abs(got[ys, xs] - ref)) < TOL[precision], precision
+
+
+# ----------------------------------------------------------------- edge cases
+def test_edge_constant_and_tiny(torch, abf):
+    for shape in [(1, 1), (1, 17), (17, 1), (3, 4)]:
+        f = np.full(shape, 12.5, dtype=np.float32)
+        for prec in ("fp64", "mixed"):
+            out = abf.fast(dev(torch, f), dev(torch, np.full(shape, 9.0)), rho=5, N=6, precision=prec)
+            assert np.array_equal(out.cpu().numpy().astype(np.float64), f.astype(np.float64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_edge_sigma_inf_and_theta_far(torch, abf, precision):
+    f = rect_scene(3, 40, 50, n_rect=4, noise=10, side_lo=4, side_hi=20)
+    sg = np.full(f.shape, np.inf, dtype=np.float32)
+    got = abf.fast(dev(torch, f), dev(torch, sg), rho=2, N=5, precision=precision).cpu().numpy()
+    ref = oracle.fast_abf(f, None, sg, "box", 2, 5)
+    assert np.max(np.abs(got - ref)) < TOL[precision]
+    th = (f + 300.0).astype(np.float32)   # centre far above every window
+    sg2 = np.full(f.shape, 15.0, dtype=np.float32)
+    got = abf.fast(dev(torch, f), dev(torch, sg2), theta=dev(torch, th), rho=2, N=5,
+                   precision=precision).cpu().numpy()
+    ref = oracle.fast_abf(f, th, sg2, "box", 2, 5)
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - ref)) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_edge_window_larger_than_image(torch, abf, precision):
+    f = rect_scene(9, 9, 23, n_rect=3, noise=10, side_lo=2, side_hi=6)
+    sg = np.full(f.shape, 25.0, dtype=np.float32)
+    got = abf.fast(dev(torch, f), dev(torch, sg), rho=30, N=6, precision=precision).cpu().numpy()
+    ref = oracle.fast_abf(f, None, sg, "box", 30, 6)
+    assert np.max(np.abs(got - ref)) < TOL[precision]
+
+
+# ----------------------------------------------------------------- brute force
+@pytest.mark.parametrize("kernel,R", [("box", 3), ("gaussian", 7)])
+def test_bruteforce_matches_oracle(torch, abf, kernel, R):
+    f = rect_scene(13, 80, 140, n_rect=5, noise=10, side_lo=6, side_hi=40)
+    zeta = smooth_field(np.random.default_rng(1), *f.shape, -20, 20)
+    th = (f + zeta).astype(np.float32)
+    sg = smooth_field(np.random.default_rng(2), *f.shape, 5, 40)
+    ref = oracle.brute_abf(f, th, sg, kernel, R)
+    g64 = abf.bruteforce(dev(torch, f), dev(torch, sg), theta=dev(torch, th), kernel=kernel, rho=R,
+                         precision="fp64").cpu().numpy()
+    g32 = abf.bruteforce(dev(torch, f), dev(torch, sg), theta=dev(torch, th), kernel=kernel, rho=R,
+                         precision="mixed").cpu().numpy()
+    assert np.max(np.abs(g64 - ref)) < 1e-9
+    assert np.max(np.abs(g32 - ref)) < 2e-3
+
+
+# ----------------------------------------------------------------- API properties
+def test_batched_equals_single_and_deterministic(torch, abf):
+    items, singles = [], []
+    for i, (h, w, kernel, R, N) in enumerate([(64, 100, "box", 3, 5), (130, 70, "gaussian", 5, 6),
+                                              (33, 257, "box", 20, 8)]):
+        f = rect_scene(100 + i, h, w, n_rect=4, noise=10, side_lo=4, side_hi=30)
+        sg = smooth_field(np.random.default_rng(i), h, w, 10, 30)
+        it = dict(img=dev(torch, f), sigma=dev(torch, sg), kernel=kernel, rho=R, N=N)
+        items.append(it)
+        singles.append(abf.fast(it["img"], it["sigma"], kernel=kernel, rho=R, N=N))
+    outs = abf.fast_batched(items)
+    outs2 = abf.fast_batched(items)
+    torch.cuda.synchronize()
+    for a, b, c in zip(outs, singles, outs2):
+        assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_stack_reuse_for_new_theta_sigma(torch, abf):
+    f = rect_scene(41, 90, 120, n_rect=5, noise=10, side_lo=6, side_hi=40)
+    st = abf.moment_stack(dev(torch, f), rho=4, N=6, precision="mixed")
+    for seed in range(3):
+        sg = smooth_field(np.random.default_rng(seed), *f.shape, 5, 50)
+        th = (f + smooth_field(np.random.default_rng(seed + 9), *f.shape, -10, 10)).astype(np.float32)
+        a = abf.range_from_stack(st, dev(torch, sg), img=dev(torch, f), theta=dev(torch, th), N=6)
+        b = abf.fast(dev(torch, f), dev(torch, sg), theta=dev(torch, th), rho=4, N=6)
+        assert torch.equal(a, b)
