@@ -9,9 +9,12 @@
 // sum_r ell_kr mu_r for the mu_r of eq. (hist_moments_new).
 //
 // Numerics. Power sums are FP64 and taken about a per-wave origin c (the
-// window mid-range at the centre of the wave's tile) instead of 0, which
-// shrinks the binomial shift's cancellation: its error grows like
-// ((|mid_i - c| + half_i) / half_i)^k times the rounding of the sums.
+// mid-range of the window bounds sampled over the wave's tile) instead of
+// 0, which shrinks the binomial shift's cancellation: its error grows like
+// rho^k, rho = (|mid_i - c| + half_i) / half_i, times the rounding of the
+// sums. A pixel whose rho^N exceeds a precision-dependent limit (nearly flat
+// windows far from c) is recomputed directly from its window by the whole
+// wave, so the stack is accurate for every input.
 //
 // Work decomposition (box kernel). One wave owns a strip of 256 padded
 // columns (4 consecutive columns per lane) and a segment of TH output rows.
@@ -51,19 +54,27 @@ __device__ __forceinline__ double wave_inclusive_scan(double v, int lane) {
 }
 
 // Per-pixel epilogue: m[1..N] are the window moments of u = f - c (m[0] = 1).
-// Writes a~_1..a~_N (or zeros if alpha == beta).
-template <int N, typename TS>
-__device__ __forceinline__ void store_legendre(double (&m)[N + 1], float a, float b, double c,
-                                               TS* __restrict__ mom, long long plane,
-                                               long long idx) {
+// Computes a~_1..a~_N into m[1..N] and returns false, or returns true when
+// the binomial shift is too ill-conditioned for the requested precision
+// (the caller then recomputes the pixel directly). alpha == beta gives 0s.
+template <int N>
+__device__ __forceinline__ bool legendre_from_moments(double (&m)[N + 1], float a, float b,
+                                                      double c, double cond_max) {
   constexpr LegTable LT{};
   if (a == b) {
 #pragma unroll
-    for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(0);
-    return;
+    for (int k = 1; k <= N; ++k) m[k] = 0.0;
+    return false;
   }
   const double mid = 0.5 * ((double)a + (double)b) - c;
   const double half = 0.5 * ((double)b - (double)a);
+  // The shift below amplifies the rounding of m_r by about
+  // rho^k, rho = (|mid| + half) / half.
+  const double rho = (fabs(mid) + half) / half;
+  double rn = rho;
+#pragma unroll
+  for (int k = 1; k < N; ++k) rn *= rho;
+  if (!(rn <= cond_max)) return true;
   // binomial shift of the moments to the origin mid (Prop. 3):
   // nu_k = sum_r C(k, r) (-mid)^(k-r) m_r, by repeated synthetic steps
   const double s = -mid;
@@ -80,13 +91,124 @@ __device__ __forceinline__ void store_legendre(double (&m)[N + 1], float a, floa
     sc *= ih;
   }
   // Legendre moments a~_k = sum_r L[k][r] nu_r (only r = k, k-2, ... are non-zero)
+  double out[N + 1];
 #pragma unroll
   for (int k = 1; k <= N; ++k) {
     double acc = 0.0;
 #pragma unroll
     for (int r = k; r >= 0; r -= 2) acc = fma(LT.L[k][r], m[r], acc);
-    mom[(k - 1) * plane + idx] = TS(acc);
+    out[k] = acc;
   }
+#pragma unroll
+  for (int k = 1; k <= N; ++k) m[k] = out[k];
+  return false;
+}
+
+// Direct evaluation of a~_k = sum_j omega_j P_k(z_j) for one pixel (y, x),
+// z_j = (f(i-j) - mid) / half, by the whole wave: lanes split the window's
+// taps, each evaluates P_1..P_N by the three-term recurrence, and the
+// partial sums are reduced across the wave. Used for the rare pixels whose
+// shift is ill-conditioned. wts == nullptr means box weights.
+template <int N>
+__device__ __forceinline__ void direct_legendre(const float* __restrict__ img, long long pitch,
+                                                int H, int W, int R, int y, int x, float a,
+                                                float b, const double* __restrict__ wts,
+                                                double norm, int lane, double (&acc)[N + 1]) {
+  const double mid = 0.5 * ((double)a + (double)b);
+  const double ih = 2.0 / ((double)b - (double)a);
+  const int w = 2 * R + 1;
+  const int n = w * w;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) acc[k] = 0.0;
+  for (int t = lane; t < n; t += kWave) {
+    const int dy = t / w - R, dx = t - (t / w) * w - R;
+    const int yy = min(max(y + dy, 0), H - 1), xx = min(max(x + dx, 0), W - 1);
+    const double z = ((double)img[(long long)yy * pitch + xx] - mid) * ih;
+    const double wt = wts ? wts[dy + R] * wts[dx + R] : 1.0;
+    double p0 = 1.0, p1 = z;
+    acc[1] = fma(wt, p1, acc[1]);
+#pragma unroll
+    for (int k = 2; k <= N; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      acc[k] = fma(wt, p2, acc[k]);
+      p0 = p1;
+      p1 = p2;
+    }
+  }
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    acc[k] = v * norm;
+  }
+}
+
+// Epilogue for one output row of a wave: lanes take consecutive output
+// columns j0 + lane; `sum_k(j, k)` returns the normalised window moment of
+// u^(k+1) for strip column j. Ill-conditioned pixels are recomputed by the
+// whole wave with direct_legendre.
+template <int N, typename TS, typename SumFn>
+__device__ __forceinline__ void epilogue_row(SumFn sum_k, int y, int xo, int O, int W, int H,
+                                             int R, const float* __restrict__ img, long long pitch,
+                                             const float* __restrict__ alpha,
+                                             const float* __restrict__ beta, long long sp,
+                                             double c, double cond_max,
+                                             const double* __restrict__ wts, double norm,
+                                             TS* __restrict__ mom, long long plane, int lane) {
+  for (int j0 = 0; j0 < O; j0 += kWave) {
+    const int j = j0 + lane;
+    const bool valid = j < O && xo + j < W;
+    const int x = valid ? xo + j : xo;
+    const long long idx = (long long)y * sp + x;
+    float a = 0.f, b = 0.f;
+    bool bad = false;
+    double m[N + 1];
+    if (valid) {
+      m[0] = 1.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) m[k + 1] = sum_k(j, k);
+      a = alpha[idx];
+      b = beta[idx];
+      bad = legendre_from_moments<N>(m, a, b, c, cond_max);
+      if (!bad) {
+#pragma unroll
+        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
+      }
+    }
+    unsigned long long mask = __ballot(valid && bad);
+    while (mask) {
+      const int l = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const int xl = __shfl(x, l, kWave);
+      const float al = __shfl(a, l, kWave), bl = __shfl(b, l, kWave);
+      double acc[N + 1];
+      direct_legendre<N>(img, pitch, H, W, R, y, xl, al, bl, wts, norm, lane, acc);
+      if (lane == 0) {
+        const long long il = (long long)y * sp + xl;
+#pragma unroll
+        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
+      }
+    }
+  }
+}
+
+// Origin of a wave's power sums: the mid-range of the window bounds sampled
+// on an 8 x 8 grid over the wave's output tile.
+__device__ __forceinline__ double wave_origin(const float* __restrict__ alpha,
+                                              const float* __restrict__ beta, long long sp,
+                                              int y0, int y1, int xo, int O, int W, int lane) {
+  const int gy = lane >> 3, gx = lane & 7;
+  const int yy = min(y0 + (gy * (y1 - 1 - y0)) / 7, y1 - 1);
+  const int xx = min(xo + (gx * (O - 1)) / 7, W - 1);
+  float lo = alpha[(long long)yy * sp + xx];
+  float hi = beta[(long long)yy * sp + xx];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, off, kWave));
+    hi = fmaxf(hi, __shfl_xor(hi, off, kWave));
+  }
+  return 0.5 * ((double)lo + (double)hi);
 }
 
 struct StripGeom {
@@ -101,7 +223,7 @@ template <int N, typename TS>
 __global__ __launch_bounds__(kWaves * kWave) void moments_box(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, StripGeom g) {
+    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max) {
   __shared__ double sh[kWaves][N][kStrip];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
@@ -113,9 +235,7 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
   const int y1 = min(H, y0 + g.TH);
   const int xo = strip * g.O;            // first output column of the strip
   const int xs = xo - g.Rpad;            // padded column 0
-  const int xc = min(W - 1, xo + g.O / 2);
-  const int yc = min(H - 1, y0 + g.TH / 2);
-  const double c = 0.5 * ((double)alpha[(long long)yc * sp + xc] + (double)beta[(long long)yc * sp + xc]);
+  const double c = wave_origin(alpha, beta, sp, y0, y1, xo, g.O, W, lane);
 
   int cx[kV];
 #pragma unroll
@@ -175,21 +295,14 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
       d[3] = incl;
     }
     wave_sync();
-    for (int j = lane; j < g.O; j += kWave) {
-      const int x = xo + j;
-      if (x >= W) break;
+    auto sum_k = [&](int j, int k) -> double {
       const int e = g.Rpad + j;
-      double m[N + 1];
-      m[0] = 1.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const double hi = sh[wv][k][e + R];
-        const double lo = (e - R - 1 >= 0) ? sh[wv][k][e - R - 1] : 0.0;
-        m[k + 1] = (hi - lo) * inv_area;
-      }
-      const long long idx = (long long)y * sp + x;
-      store_legendre<N, TS>(m, alpha[idx], beta[idx], c, mom, plane, idx);
-    }
+      const double hi = sh[wv][k][e + R];
+      const double lo = (e - R - 1 >= 0) ? sh[wv][k][e - R - 1] : 0.0;
+      return (hi - lo) * inv_area;
+    };
+    epilogue_row<N, TS>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c, cond_max,
+                        nullptr, inv_area, mom, plane, lane);
     wave_sync();
   }
 }
@@ -198,7 +311,7 @@ template <int N, typename TS>
 __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
     const float* __restrict__ img, long long pitch, int H, int W, int R, double inv2s2,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, StripGeom g) {
+    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max) {
   __shared__ double sh[kWaves][N][kStrip];
   __shared__ double wts[2 * kRhoMax + 1];
   for (int i = threadIdx.x; i <= 2 * R; i += blockDim.x) {
@@ -220,9 +333,7 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
   const int y1 = min(H, y0 + g.TH);
   const int xo = strip * g.O;
   const int xs = xo - g.Rpad;
-  const int xc = min(W - 1, xo + g.O / 2);
-  const int yc = min(H - 1, y0 + g.TH / 2);
-  const double c = 0.5 * ((double)alpha[(long long)yc * sp + xc] + (double)beta[(long long)yc * sp + xc]);
+  const double c = wave_origin(alpha, beta, sp, y0, y1, xo, g.O, W, lane);
 
   int cx[kV];
 #pragma unroll
@@ -253,22 +364,14 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
 #pragma unroll
       for (int v = 0; v < kV; ++v) sh[wv][k][kV * lane + v] = S[k][v];
     wave_sync();
-    for (int j = lane; j < g.O; j += kWave) {
-      const int x = xo + j;
-      if (x >= W) break;
+    auto sum_k = [&](int j, int k) -> double {
       const int e = g.Rpad + j;
-      double m[N + 1];
-      m[0] = 1.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) m[k + 1] = 0.0;
-      for (int dx = -R; dx <= R; ++dx) {
-        const double wx = wts[dx + R] * iz;
-#pragma unroll
-        for (int k = 0; k < N; ++k) m[k + 1] = fma(wx, sh[wv][k][e + dx], m[k + 1]);
-      }
-      const long long idx = (long long)y * sp + x;
-      store_legendre<N, TS>(m, alpha[idx], beta[idx], c, mom, plane, idx);
-    }
+      double acc = 0.0;
+      for (int dx = -R; dx <= R; ++dx) acc = fma(wts[dx + R], sh[wv][k][e + dx], acc);
+      return acc * iz;
+    };
+    epilogue_row<N, TS>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c, cond_max,
+                        wts, iz * iz, mom, plane, lane);
     wave_sync();
   }
 }
@@ -292,15 +395,19 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
                             double sigma_s, int R, const float* alpha, const float* beta,
                             long long sp, TS* mom, long long plane, hipStream_t stream) {
   const StripGeom g = make_geom(h, w, R, 4096);
+  // largest tolerated shift amplification: FP64 stack keeps ~1e-8 relative
+  // headroom; the FP32 stack only needs to stay below its own rounding
+  const double cond_max = sizeof(TS) == 8 ? 1e8 : 1e12;
   const int waves = g.n_strips * g.n_segs;
   dim3 grid((waves + kWaves - 1) / kWaves);
   if (kind == 0) {
     hipLaunchKernelGGL((moments_box<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
-                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g);
+                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max);
   } else {
     const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
     hipLaunchKernelGGL((moments_gauss<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
-                       img, pitch, h, w, R, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, g);
+                       img, pitch, h, w, R, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, g,
+                       cond_max);
   }
   return hipGetLastError();
 }

@@ -11,8 +11,9 @@
 //   psi = exp(-lambda (t - t0)^2), and g^ = alpha + (beta-alpha) T1/T2
 //   (eq. BFfinal).
 //
-// Two evaluations of T1, T2, chosen per pixel by lambda:
-//   lambda >= kLamSplit: the paper's route. I_0 from two error functions
+// Two evaluations of T1, T2, chosen per pixel by lambda and by how far t0
+// lies outside [0, 1] (d = dist(t0, [0,1])):
+//   lambda >= kLamSplit and d sqrt(lambda) < kOutside: the paper's route. I_0 from two error functions
 //     (eq. I_0), I_1 (eq. I_1), I_2..I_{N+1} by the integration-by-parts
 //     recursion (eq. F_forward), T1 = sum c_k I_{k+1}, T2 = sum c_k I_k.
 //     Every I_k is scaled by exp(lambda d^2), d = dist(t0, [0,1]), so that
@@ -20,10 +21,14 @@
 //     the erf difference is written with erfcx (scaled complementary error
 //     function), which has no cancellation when both arguments share a
 //     sign. The common factor cancels in T1/T2.
-//   lambda < kLamSplit: the recursion divides by 2 lambda and loses
-//     accuracy as lambda -> 0, so T1 and T2 are integrated directly with a
-//     16-node Gauss-Legendre rule on [0,1], p evaluated by the Clenshaw
-//     recurrence in the Legendre basis (no monomial cancellation).
+//   otherwise: the recursion divides by 2 lambda and loses accuracy as
+//     lambda -> 0, and it multiplies errors by about t0 per step when t0 is
+//     far outside [0,1]. There T1 and T2 are integrated directly with a
+//     16-node Gauss-Legendre rule on the part of [0,1] where the scaled
+//     Gaussian exceeds e^-kSupport (all of [0,1] for small lambda; a short
+//     interval next to the nearer end when t0 is far outside), p evaluated
+//     by the Clenshaw recurrence in the Legendre basis (no monomial
+//     cancellation).
 // Post-rules: if T2 <= 0 or T1/T2 is not finite, F = I_1/I_0 (the N = 0
 // estimate); ABF_FLAG_CLAMP clips F to [0,1]. alpha == beta gives f(i).
 #include "abf_internal.h"
@@ -32,6 +37,8 @@ namespace abf {
 namespace {
 
 constexpr double kLamSplit = 4.0;
+constexpr double kOutside = 1.5;
+constexpr double kSupport = 30.0;
 constexpr double kSqrtPi = 1.7724538509055160273;
 
 struct GLArgs {
@@ -67,8 +74,10 @@ __global__ __launch_bounds__(256) void range_kernel(
 #pragma unroll
   for (int k = 1; k <= N; ++k) ak[k] = (2.0 * k + 1.0) * (double)mom[(k - 1) * plane + idx];
 
+  const double ts = fmin(fmax(t0, 0.0), 1.0);
+  const double dist = fabs(t0 - ts);
   double T1, T2, F0;
-  if (lam >= kLamSplit) {
+  if (lam >= kLamSplit && dist * sqrt(lam) < kOutside) {
     double c[N + 1];
 #pragma unroll
     for (int r = 0; r <= N; ++r) {
@@ -79,7 +88,6 @@ __global__ __launch_bounds__(256) void range_kernel(
     }
     const double sl = sqrt(lam);
     const double A = -sl * t0, B = sl * (1.0 - t0);
-    const double ts = fmin(fmax(t0, 0.0), 1.0);
     const double dd = t0 - ts;
     const double s = lam * dd * dd;
     const double E0 = exp(s - A * A);    // exp(-lam t0^2) * e^s
@@ -108,12 +116,15 @@ __global__ __launch_bounds__(256) void range_kernel(
       Im1 = Ik;
     }
   } else {
-    const double ts = fmin(fmax(t0, 0.0), 1.0);
+    // support of the scaled Gaussian exp(-lam ((t-t0)^2 - dist^2)) above e^-kSupport
+    const double L = lam > 0.0 ? sqrt(dist * dist + kSupport / lam) - dist : 2.0;
+    const double lo = fmax(0.0, ts - L), hi = fmin(1.0, ts + L);
+    const double span = hi - lo;
     T1 = T2 = 0.0;
     double J0 = 0.0, J1 = 0.0;
 #pragma unroll
     for (int q = 0; q < kGLNodes; ++q) {
-      const double t = gl.t[q];
+      const double t = fma(span, gl.t[q], lo);
       const double z = 2.0 * t - 1.0;
       // Clenshaw: p = sum_k ak[k] P_k(z)
       double b1 = 0.0, b2 = 0.0;
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(256) void range_kernel(
         b2 = b1;
         b1 = bk;
       }
-      const double wpsi = gl.w[q] * exp(-lam * (t - ts) * (t + ts - 2.0 * t0));
+      const double wpsi = span * gl.w[q] * exp(-lam * (t - ts) * (t + ts - 2.0 * t0));
       J0 += wpsi;
       J1 = fma(wpsi, t, J1);
       T2 = fma(wpsi, b1, T2);
