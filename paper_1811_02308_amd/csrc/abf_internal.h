@@ -12,14 +12,17 @@ constexpr int kNMax = 8;
 constexpr int kRhoMax = 96;
 constexpr int kWave = 64;
 
-// Gauss-Legendre rule on [0, 1] used by the range kernel for small lambda.
+// Gauss-Legendre rules on [0, 1] used by the range kernel: 16 nodes for the
+// FP64 path, 12 for the mixed path.
 constexpr int kGLNodes = 16;
+constexpr int kGLNodesMixed = 12;
 struct GLRule {
   double t[kGLNodes];
   double w[kGLNodes];
 };
-// Computed once on the host (Newton iteration on P_Q), see api.cpp.
-const GLRule& gl_rule();
+// Computed once per node count on the host (Newton iteration on P_Q), see
+// api.cpp. q must be kGLNodes or kGLNodesMixed (entries beyond q are 0).
+const GLRule& gl_rule(int q);
 
 // Coefficients of the Legendre polynomial P_k(z) = sum_r L[k][r] z^r
 // (three-term recurrence (k+1) P_{k+1} = (2k+1) z P_k - k P_{k-1}).

@@ -7,7 +7,8 @@
 // window [x, x+2R] is the tail of one block plus the head of the next, so
 //     min = min(suffix_min(x), prefix_min(x + 2R)).
 //
-// One kernel does a row pass and writes its result TRANSPOSED, so the
+// For R <= 24 a single tiled kernel does both passes in LDS (below). For
+// larger R, one kernel does a row pass and writes its result TRANSPOSED, so the
 // column pass is the same row kernel run on the transposed intermediate
 // (both passes read and write rows, coalesced). A workgroup stages
 // ROWS padded rows in LDS; phase 1 writes the block suffixes into the
@@ -102,6 +103,109 @@ __global__ __launch_bounds__(kThreads) void vh_rows(
   }
 }
 
+// Single-pass tiled variant for R <= kTileRMax: a workgroup loads the
+// (kMTY + 2R) x (kMTX + 2R) padded tile of f into LDS once, then
+//   horizontal: a thread takes 8 adjacent outputs of one padded row. The
+//     8 windows [v, v+2R] (v = 0..7) share the core [7, 2R], so the thread
+//     takes the core's min/max once, a suffix over [v, 6] and a prefix over
+//     [2R+1, 2R+v]: about (2R + 30) comparisons per 8 outputs.
+//   vertical: the same on columns of the horizontal result, 8 output rows
+//     per thread, written straight to alpha/beta.
+// No intermediate leaves the workgroup; f is read once (+ halo from L2).
+constexpr int kMTX = 64, kMTY = 32, kTileRMax = 24;
+
+template <typename Get>
+__device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&mx)[8]) {
+  // windows [v, v + 2R] of the sequence get(0 .. 7 + 2R)
+  if (2 * R < 7) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      float lo = INFINITY, hi = -INFINITY;
+      for (int i = 0; i <= 2 * R; ++i) {
+        const float2 q = get(v + i);
+        lo = fminf(lo, q.x);
+        hi = fmaxf(hi, q.y);
+      }
+      mn[v] = lo;
+      mx[v] = hi;
+    }
+    return;
+  }
+  float clo = INFINITY, chi = -INFINITY;
+  for (int i = 7; i <= 2 * R; ++i) {
+    const float2 q = get(i);
+    clo = fminf(clo, q.x);
+    chi = fmaxf(chi, q.y);
+  }
+  // suffixes over [v, 6], v = 6 .. 0
+  float slo = clo, shi = chi;
+#pragma unroll
+  for (int v = 6; v >= 0; --v) {
+    const float2 q = get(v);
+    slo = fminf(slo, q.x);
+    shi = fmaxf(shi, q.y);
+    mn[v] = slo;
+    mx[v] = shi;
+  }
+  mn[7] = clo;
+  mx[7] = chi;
+  // prefixes over [2R+1, 2R+v], v = 1 .. 7
+  float plo = INFINITY, phi = -INFINITY;
+#pragma unroll
+  for (int v = 1; v < 8; ++v) {
+    const float2 q = get(2 * R + v);
+    plo = fminf(plo, q.x);
+    phi = fmaxf(phi, q.y);
+    mn[v] = fminf(mn[v], plo);
+    mx[v] = fmaxf(mx[v], phi);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void minmax_tile(
+    const float* __restrict__ img, long long pitch, int H, int W, int R,
+    float* __restrict__ out_a, float* __restrict__ out_b, long long op) {
+  extern __shared__ float lds[];
+  const int EX = kMTX + 2 * R, EY = kMTY + 2 * R;
+  float* tile = lds;                                       // EY x EX
+  float2* hres = reinterpret_cast<float2*>(lds + ((EY * EX + 1) & ~1));   // EY x kMTX
+  const int x0 = blockIdx.x * kMTX, y0 = blockIdx.y * kMTY;
+  for (int i = threadIdx.x; i < EY * EX; i += kThreads) {
+    const int r = i / EX, c = i - r * EX;
+    const int gy = min(max(y0 - R + r, 0), H - 1);
+    const int gx = min(max(x0 - R + c, 0), W - 1);
+    tile[i] = img[(long long)gy * pitch + gx] + 0.0f;
+  }
+  __syncthreads();
+  // horizontal: item = (padded row, group of 8 outputs); rows vary fastest
+  for (int it = threadIdx.x; it < EY * (kMTX / 8); it += kThreads) {
+    const int r = it % EY, g = it / EY;
+    const float* row = tile + r * EX + 8 * g;
+    float mn[8], mx[8];
+    slide8([&](int i) { const float v = row[i]; return make_float2(v, v); }, R, mn, mx);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) hres[r * kMTX + 8 * g + v] = make_float2(mn[v], mx[v]);
+  }
+  __syncthreads();
+  // vertical: item = (output column, group of 8 output rows); columns fastest
+  for (int it = threadIdx.x; it < kMTX * (kMTY / 8); it += kThreads) {
+    const int c = it % kMTX, g = it / kMTX;
+    const float2* col = hres + (8 * g) * kMTX + c;
+    float mn[8], mx[8];
+    slide8([&](int i) { return col[i * kMTX]; }, R, mn, mx);
+    const int x = x0 + c;
+    if (x < W) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int y = y0 + 8 * g + v;
+        if (y < H) {
+          out_a[(long long)y * op + x] = mn[v];
+          out_b[(long long)y * op + x] = mx[v];
+        }
+      }
+    }
+  }
+}
+
 int rows_per_block(int R) {
   // keep the LDS footprint ROWS * (2*kTX + 2R) * 8 bytes within 64 KiB
   int rows = 64;
@@ -117,6 +221,15 @@ hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rh
   // The window clipped to the image is the same for any radius >= dim - 1.
   const int Rh = rho < w - 1 ? rho : w - 1;
   const int Rv = rho < h - 1 ? rho : h - 1;
+  if (rho <= kTileRMax) {
+    // clamping of the padded tile makes any radius exact; use rho itself
+    dim3 grid((w + kMTX - 1) / kMTX, (h + kMTY - 1) / kMTY);
+    const int EX = kMTX + 2 * rho, EY = kMTY + 2 * rho;
+    const size_t lds = (size_t)((EY * EX + 1) & ~1) * sizeof(float) + (size_t)EY * kMTX * sizeof(float2);
+    hipLaunchKernelGGL(minmax_tile, grid, dim3(kThreads), lds, stream, img, pitch, h, w, rho,
+                       alpha, beta, out_pitch);
+    return hipGetLastError();
+  }
   const long long tp = ((long long)h + 63) / 64 * 64;   // pitch of transposed rows
   float2* t = static_cast<float2*>(scratch);
   {

@@ -27,8 +27,9 @@
 // reads the prefix from LDS with lanes mapped to consecutive output
 // columns, so alpha/beta loads and moment stores are coalesced.
 //
-// Gaussian kernel: same wave/strip layout; vertical and horizontal sums
-// are direct weighted sums (O(R) per pixel, weights in LDS).
+// Gaussian kernel: a 2-D tile with register-blocked separable weighted sums
+// (O(R) per pixel); for radii too large for its LDS tile, the strip layout
+// of the box kernel with direct weighted sums.
 #include "abf_internal.h"
 
 namespace abf {
@@ -44,12 +45,28 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// v + (value of v `ctrl` DPP positions away), 0 where the source lane is
+// outside the pattern (rows masked by row_mask keep 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffLL), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROW_MASK, 0xf, false);
+  const long long tb = ((long long)hi << 32) | (long long)(unsigned)lo;
+  return v + __longlong_as_double(tb);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP lane moves:
+// row_shr 1, 2, 4, 8 scan each row of 16 lanes, then row_bcast 15 and 31
+// carry row totals into the rows above.
 __device__ __forceinline__ double wave_inclusive_scan(double v, int lane) {
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const double t = __shfl_up(v, off, kWave);
-    if (lane >= off) v += t;
-  }
+  (void)lane;
+  v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 -> rows 1, 3
+  v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 -> rows 2, 3
   return v;
 }
 
@@ -376,6 +393,153 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
   }
 }
 
+// Gaussian kernel, tiled: a workgroup computes a kTY x TX tile of outputs.
+// Phase 1 (vertical): thread t owns padded column t, reads its kTY + 2R
+// inputs once (coalesced across threads), forms the powers once per input
+// and accumulates the kTY x N vertical weighted sums in registers; the sums
+// go to LDS. Phase 2 (horizontal): a thread owns 4 adjacent output columns
+// of one row and accumulates their 4 x N horizontal weighted sums from the
+// (4 + 2R) LDS columns they span. Phase 3: shift and Legendre basis per
+// pixel (same epilogue as the box kernel, with the exact recompute for
+// ill-conditioned pixels). Work per pixel is O(R), as for the paper's
+// direct convolution.
+constexpr int kTY = 8;
+
+template <int N, typename TS>
+__global__ __launch_bounds__(256) void moments_gauss_tile(
+    const float* __restrict__ img, long long pitch, int H, int W, int R, int TX, double inv2s2,
+    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    TS* __restrict__ mom, long long plane, double cond_max) {
+  extern __shared__ double vsum[];            // [N][kTY][E]
+  __shared__ double wts[2 * kRhoMax + 1];
+  __shared__ double origin;
+  const int E = TX + 2 * R;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * kTY;
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  for (int i = t; i <= 2 * R; i += blockDim.x) {
+    const double d = (double)(i - R);
+    wts[i] = exp(-d * d * inv2s2);
+  }
+  if (t < kWave) {
+    const int y1 = min(H, y0 + kTY);
+    const double c = wave_origin(alpha, beta, sp, y0, y1, x0, min(TX, W - x0), W, lane);
+    if (t == 0) origin = c;
+  }
+  __syncthreads();
+  double z = 0.0;
+  for (int i = 0; i <= 2 * R; ++i) z += wts[i];
+  const double iz = 1.0 / z;
+  const double c = origin;
+
+  // phase 1: vertical sums for padded column t
+  if (t < E) {
+    const int cx = min(max(x0 - R + t, 0), W - 1);
+    double acc[kTY][N];
+#pragma unroll
+    for (int r = 0; r < kTY; ++r)
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc[r][k] = 0.0;
+    for (int i = 0; i < kTY + 2 * R; ++i) {
+      const int yy = min(max(y0 - R + i, 0), H - 1);
+      const double u = (double)img[(long long)yy * pitch + cx] - c;
+      double pw[N];
+      pw[0] = u;
+#pragma unroll
+      for (int k = 1; k < N; ++k) pw[k] = pw[k - 1] * u;
+#pragma unroll
+      for (int r = 0; r < kTY; ++r) {
+        const int d = i - r;
+        if (d >= 0 && d <= 2 * R) {
+          const double wv = wts[d];
+#pragma unroll
+          for (int k = 0; k < N; ++k) acc[r][k] = fma(wv, pw[k], acc[r][k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kTY; ++r)
+#pragma unroll
+      for (int k = 0; k < N; ++k) vsum[(k * kTY + r) * E + t] = acc[r][k];
+  }
+  __syncthreads();
+
+  // phase 2: horizontal sums for 4 adjacent outputs of one row
+  const int groups = TX / 4;
+  const int r = t / groups, gq = t - r * groups;
+  const bool active = r < kTY;
+  const int xl = 4 * gq;
+  double m4[4][N + 1];
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int k = 0; k <= N; ++k) m4[v][k] = 0.0;
+    for (int j = 0; j < 4 + 2 * R; ++j) {
+      double val[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) val[k] = vsum[(k * kTY + r) * E + xl + j];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int d = j - v;
+        if (d >= 0 && d <= 2 * R) {
+          const double wv = wts[d];
+#pragma unroll
+          for (int k = 0; k < N; ++k) m4[v][k + 1] = fma(wv, val[k], m4[v][k + 1]);
+        }
+      }
+    }
+  }
+  // phase 3: per-pixel epilogue (all lanes take part in the wave ballots)
+  const double norm = iz * iz;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int y = y0 + r, x = x0 + xl + v;
+    const bool valid = active && y < H && x < W && xl + v < TX;
+    const long long idx = (long long)(valid ? y : 0) * sp + (valid ? x : 0);
+    float a = 0.f, b = 0.f;
+    bool bad = false;
+    if (valid) {
+      double m[N + 1];
+      m[0] = 1.0;
+#pragma unroll
+      for (int k = 1; k <= N; ++k) m[k] = m4[v][k] * norm;
+      a = alpha[idx];
+      b = beta[idx];
+      bad = legendre_from_moments<N>(m, a, b, c, cond_max);
+      if (!bad) {
+#pragma unroll
+        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
+      }
+    }
+    unsigned long long mask = __ballot(valid && bad);
+    while (mask) {
+      const int l = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const int yl = __shfl(y, l, kWave), xl2 = __shfl(x, l, kWave);
+      const float al = __shfl(a, l, kWave), bl = __shfl(b, l, kWave);
+      double acc[N + 1];
+      direct_legendre<N>(img, pitch, H, W, R, yl, xl2, al, bl, wts, norm, lane, acc);
+      if (lane == 0) {
+        const long long il = (long long)yl * sp + xl2;
+#pragma unroll
+        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
+      }
+    }
+  }
+}
+
+// Output columns per Gaussian tile: at most 128, with the LDS tile
+// kTY x (TX + 2R) x N doubles within 64 KiB; 0 if R is too large.
+int gauss_tile_tx(int R, int N) {
+  int e = 1024 / N;
+  if (e > 256) e = 256;
+  int tx = e - 2 * R;
+  if (tx > 128) tx = 128;
+  tx &= ~3;
+  return tx >= 4 ? tx : 0;
+}
+
 StripGeom make_geom(int H, int W, int R, int target_waves) {
   StripGeom g;
   g.Rpad = (R + kV - 1) / kV * kV;
@@ -394,7 +558,7 @@ template <int N, typename TS>
 hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int kind,
                             double sigma_s, int R, const float* alpha, const float* beta,
                             long long sp, TS* mom, long long plane, hipStream_t stream) {
-  const StripGeom g = make_geom(h, w, R, 4096);
+  const StripGeom g = make_geom(h, w, R, 2560);
   // largest tolerated shift amplification: FP64 stack keeps ~1e-8 relative
   // headroom; the FP32 stack only needs to stay below its own rounding
   const double cond_max = sizeof(TS) == 8 ? 1e8 : 1e12;
@@ -405,6 +569,14 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
                        img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max);
   } else {
     const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
+    const int tx = gauss_tile_tx(R, N);
+    if (tx > 0) {
+      dim3 tg((w + tx - 1) / tx, (h + kTY - 1) / kTY);
+      const size_t lds = (size_t)N * kTY * (tx + 2 * R) * sizeof(double);
+      hipLaunchKernelGGL((moments_gauss_tile<N, TS>), tg, dim3(256), lds, stream, img, pitch, h,
+                         w, R, tx, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, cond_max);
+      return hipGetLastError();
+    }
     hipLaunchKernelGGL((moments_gauss<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
                        img, pitch, h, w, R, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, g,
                        cond_max);

@@ -13,7 +13,7 @@
 //
 // Two evaluations of T1, T2, chosen per pixel by lambda and by how far t0
 // lies outside [0, 1] (d = dist(t0, [0,1])):
-//   lambda >= kLamSplit and d sqrt(lambda) < kOutside: the paper's route. I_0 from two error functions
+//   lambda >= lam_split(N) and d sqrt(lambda) < outside_limit: the paper's route. I_0 from two error functions
 //     (eq. I_0), I_1 (eq. I_1), I_2..I_{N+1} by the integration-by-parts
 //     recursion (eq. F_forward), T1 = sum c_k I_{k+1}, T2 = sum c_k I_k.
 //     Every I_k is scaled by exp(lambda d^2), d = dist(t0, [0,1]), so that
@@ -24,11 +24,12 @@
 //   otherwise: the recursion divides by 2 lambda and loses accuracy as
 //     lambda -> 0, and it multiplies errors by about t0 per step when t0 is
 //     far outside [0,1]. There T1 and T2 are integrated directly with a
-//     16-node Gauss-Legendre rule on the part of [0,1] where the scaled
-//     Gaussian exceeds e^-kSupport (all of [0,1] for small lambda; a short
-//     interval next to the nearer end when t0 is far outside), p evaluated
-//     by the Clenshaw recurrence in the Legendre basis (no monomial
-//     cancellation).
+//     Gauss-Legendre rule (16 nodes FP64 path, 12 nodes mixed path) on the
+//     part of [0,1] where the scaled Gaussian exceeds e^-kSupport (all of
+//     [0,1] for small lambda; a short interval next to the nearer end when
+//     t0 is far outside), p evaluated by Horner in x = 2t - 1, whose
+//     coefficients (from the Legendre moments) stay moderate, unlike the
+//     monomial coefficients c on [0,1].
 // Post-rules: if T2 <= 0 or T1/T2 is not finite, F = I_1/I_0 (the N = 0
 // estimate); ABF_FLAG_CLAMP clips F to [0,1]. alpha == beta gives f(i).
 #include "abf_internal.h"
@@ -36,9 +37,27 @@
 namespace abf {
 namespace {
 
-constexpr double kLamSplit = 4.0;
-constexpr double kOutside = 1.5;
+// Smallest lambda at which the forward recursion is used, per degree N.
+// The recursion's rounding grows roughly like N!/(2 lambda)^N; these limits
+// keep its error in F below ~1e-10 (FP64 path) and ~1e-6 (mixed path),
+// measured against 60-digit evaluations of the integrals.
+__host__ __device__ constexpr double lam_split(int N, bool mixed) {
+  return mixed ? (N <= 6 ? 0.05 : (N == 7 ? 0.12 : 0.25))
+               : (N <= 4 ? 0.1 : (N == 5 ? 0.2 : (N == 6 ? 0.5 : (N == 7 ? 1.0 : 2.0))));
+}
+// The recursion multiplies errors by about |t0| per step, so it is used only
+// while t0 is within outside_limit/sqrt(lambda) of [0, 1].
+__host__ __device__ constexpr double outside_limit(bool mixed) { return mixed ? 1.5 : 0.5; }
 constexpr double kSupport = 30.0;
+
+// 1/x from the hardware reciprocal estimate and two Newton steps (a few ulp;
+// used for parameters and the final ratio, never for exact quantities).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
 constexpr double kSqrtPi = 1.7724538509055160273;
 
 struct GLArgs {
@@ -53,6 +72,12 @@ __global__ __launch_bounds__(256) void range_kernel(
     long long tpitch, const float* __restrict__ sigma, long long spitch, int H, int W,
     unsigned flags, TO* __restrict__ out, long long opitch, GLArgs gl) {
   constexpr ShiftedLegTable SL{};
+  constexpr LegTable LT{};
+  // mixed path: 12-node rule and single-precision exponentials for the
+  // quadrature weights (their 1e-7 relative error is far below the FP32
+  // output's own resolution of the 0.05 tolerance); FP64 path: 16 nodes.
+  constexpr bool kMixed = sizeof(TO) == 4;
+  constexpr int Q = kMixed ? kGLNodesMixed : kGLNodes;
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= W || y >= H) return;
@@ -66,8 +91,8 @@ __global__ __launch_bounds__(256) void range_kernel(
   const double da = a, delta = (double)b - da;
   const double th = theta[(long long)y * tpitch + x];
   const double sg = sigma[(long long)y * spitch + x];
-  const double t0 = (th - da) / delta;
-  const double lam = delta * delta / (2.0 * sg * sg);
+  const double t0 = (th - da) * rcp(delta);
+  const double lam = isinf(sg) ? 0.0 : delta * delta * rcp(2.0 * sg * sg);
 
   double ak[N + 1];                      // (2k+1) a~_k
   ak[0] = 1.0;
@@ -77,7 +102,7 @@ __global__ __launch_bounds__(256) void range_kernel(
   const double ts = fmin(fmax(t0, 0.0), 1.0);
   const double dist = fabs(t0 - ts);
   double T1, T2, F0;
-  if (lam >= kLamSplit && dist * sqrt(lam) < kOutside) {
+  if (lam >= lam_split(N, kMixed) && dist * sqrt(lam) < outside_limit(kMixed)) {
     double c[N + 1];
 #pragma unroll
     for (int r = 0; r <= N; ++r) {
@@ -100,10 +125,10 @@ __global__ __launch_bounds__(256) void range_kernel(
     } else {
       diff = erfcx(-B) * E1 - erfcx(-A) * E0;
     }
-    const double i2l = 0.5 / lam;
-    double Im2 = 0.5 * kSqrtPi / sl * diff;          // I_0
+    const double i2l = 0.5 * rcp(lam);
+    double Im2 = 0.5 * kSqrtPi * rcp(sl) * diff;     // I_0
     double Im1 = fma(t0, Im2, (E0 - E1) * i2l);      // I_1
-    F0 = Im1 / Im2;
+    F0 = Im1 * rcp(Im2);
     T2 = c[0] * Im2;
     T1 = c[0] * Im1;
     const double e1l = E1 * i2l;
@@ -120,29 +145,41 @@ __global__ __launch_bounds__(256) void range_kernel(
     const double L = lam > 0.0 ? sqrt(dist * dist + kSupport / lam) - dist : 2.0;
     const double lo = fmax(0.0, ts - L), hi = fmin(1.0, ts + L);
     const double span = hi - lo;
+    // p in powers of x = 2t - 1: bx[r] = sum_k ak[k] L[k][r] (coefficients of
+    // moderate size, so Horner in x on [-1, 1] is well conditioned)
+    double bx[N + 1];
+#pragma unroll
+    for (int r = 0; r <= N; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = r; k <= N; k += 2) acc = fma(ak[k], LT.L[k][r], acc);
+      bx[r] = acc;
+    }
     T1 = T2 = 0.0;
     double J0 = 0.0, J1 = 0.0;
 #pragma unroll
-    for (int q = 0; q < kGLNodes; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const double t = fma(span, gl.t[q], lo);
-      const double z = 2.0 * t - 1.0;
-      // Clenshaw: p = sum_k ak[k] P_k(z)
-      double b1 = 0.0, b2 = 0.0;
+      const double x = 2.0 * t - 1.0;
+      double p = bx[N];
 #pragma unroll
-      for (int k = N; k >= 0; --k) {
-        const double bk = ak[k] + ((2.0 * k + 1.0) / (k + 1.0)) * z * b1 - ((k + 1.0) / (k + 2.0)) * b2;
-        b2 = b1;
-        b1 = bk;
+      for (int r = N - 1; r >= 0; --r) p = fma(p, x, bx[r]);
+      const double e = -lam * (t - ts) * (t + ts - 2.0 * t0);
+      double psi;
+      if (kMixed) {
+        psi = (double)__expf((float)fmax(e, -80.0));
+      } else {
+        psi = exp(e);
       }
-      const double wpsi = span * gl.w[q] * exp(-lam * (t - ts) * (t + ts - 2.0 * t0));
+      const double wpsi = span * gl.w[q] * psi;
       J0 += wpsi;
       J1 = fma(wpsi, t, J1);
-      T2 = fma(wpsi, b1, T2);
-      T1 = fma(wpsi * t, b1, T1);
+      T2 = fma(wpsi, p, T2);
+      T1 = fma(wpsi * t, p, T1);
     }
-    F0 = J1 / J0;
+    F0 = J1 * rcp(J0);
   }
-  double F = T1 / T2;
+  double F = T1 * rcp(T2);
   if (!(T2 > 0.0) || !isfinite(F)) F = F0;
   if (flags & 1u) F = fmin(fmax(F, 0.0), 1.0);
   *o = TO(fma(delta, F, da));
@@ -154,7 +191,7 @@ hipError_t launch_t(const float* alpha, const float* beta, long long sp, const v
                     long long spitch, int h, int w, unsigned flags, void* out, long long opitch,
                     hipStream_t stream) {
   GLArgs gl;
-  const GLRule& r = gl_rule();
+  const GLRule& r = gl_rule(sizeof(TO) == 4 ? kGLNodesMixed : kGLNodes);
   for (int q = 0; q < kGLNodes; ++q) {
     gl.t[q] = r.t[q];
     gl.w[q] = r.w[q];
