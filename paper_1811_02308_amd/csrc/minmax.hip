@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void vh_rows(
 //   vertical: the same on columns of the horizontal result, 8 output rows
 //     per thread, written straight to alpha/beta.
 // No intermediate leaves the workgroup; f is read once (+ halo from L2).
-constexpr int kMTX = 64, kMTY = 32, kTileRMax = 24;
+constexpr int kMTX = 64, kMTY = 32, kTileRMax = 24, kHS = kMTX + 1;
 
 template <typename Get>
 __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&mx)[8]) {
@@ -165,33 +165,37 @@ __global__ __launch_bounds__(kThreads) void minmax_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     float* __restrict__ out_a, float* __restrict__ out_b, long long op) {
   extern __shared__ float lds[];
+  // LDS row strides: odd for the padded tile and kMTX + 1 for the
+  // horizontal result, so that threads walking different rows hit
+  // different banks
   const int EX = kMTX + 2 * R, EY = kMTY + 2 * R;
-  float* tile = lds;                                       // EY x EX
-  float2* hres = reinterpret_cast<float2*>(lds + ((EY * EX + 1) & ~1));   // EY x kMTX
+  const int XS = EX | 1;
+  float* tile = lds;                                       // EY x XS
+  float2* hres = reinterpret_cast<float2*>(lds + ((EY * XS + 1) & ~1));   // EY x kHS
   const int x0 = blockIdx.x * kMTX, y0 = blockIdx.y * kMTY;
   for (int i = threadIdx.x; i < EY * EX; i += kThreads) {
     const int r = i / EX, c = i - r * EX;
     const int gy = min(max(y0 - R + r, 0), H - 1);
     const int gx = min(max(x0 - R + c, 0), W - 1);
-    tile[i] = img[(long long)gy * pitch + gx] + 0.0f;
+    tile[r * XS + c] = img[(long long)gy * pitch + gx] + 0.0f;
   }
   __syncthreads();
   // horizontal: item = (padded row, group of 8 outputs); rows vary fastest
   for (int it = threadIdx.x; it < EY * (kMTX / 8); it += kThreads) {
     const int r = it % EY, g = it / EY;
-    const float* row = tile + r * EX + 8 * g;
+    const float* row = tile + r * XS + 8 * g;
     float mn[8], mx[8];
     slide8([&](int i) { const float v = row[i]; return make_float2(v, v); }, R, mn, mx);
 #pragma unroll
-    for (int v = 0; v < 8; ++v) hres[r * kMTX + 8 * g + v] = make_float2(mn[v], mx[v]);
+    for (int v = 0; v < 8; ++v) hres[r * kHS + 8 * g + v] = make_float2(mn[v], mx[v]);
   }
   __syncthreads();
   // vertical: item = (output column, group of 8 output rows); columns fastest
   for (int it = threadIdx.x; it < kMTX * (kMTY / 8); it += kThreads) {
     const int c = it % kMTX, g = it / kMTX;
-    const float2* col = hres + (8 * g) * kMTX + c;
+    const float2* col = hres + (8 * g) * kHS + c;
     float mn[8], mx[8];
-    slide8([&](int i) { return col[i * kMTX]; }, R, mn, mx);
+    slide8([&](int i) { return col[i * kHS]; }, R, mn, mx);
     const int x = x0 + c;
     if (x < W) {
 #pragma unroll
@@ -224,8 +228,8 @@ hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rh
   if (rho <= kTileRMax) {
     // clamping of the padded tile makes any radius exact; use rho itself
     dim3 grid((w + kMTX - 1) / kMTX, (h + kMTY - 1) / kMTY);
-    const int EX = kMTX + 2 * rho, EY = kMTY + 2 * rho;
-    const size_t lds = (size_t)((EY * EX + 1) & ~1) * sizeof(float) + (size_t)EY * kMTX * sizeof(float2);
+    const int EX = kMTX + 2 * rho, EY = kMTY + 2 * rho, XS = EX | 1;
+    const size_t lds = (size_t)((EY * XS + 1) & ~1) * sizeof(float) + (size_t)EY * kHS * sizeof(float2);
     hipLaunchKernelGGL(minmax_tile, grid, dim3(kThreads), lds, stream, img, pitch, h, w, rho,
                        alpha, beta, out_pitch);
     return hipGetLastError();

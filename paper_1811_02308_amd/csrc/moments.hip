@@ -38,6 +38,12 @@ namespace {
 constexpr int kV = 4;                    // columns per lane
 constexpr int kStrip = kWave * kV;       // padded columns per wave
 constexpr int kWaves = 4;                // waves per workgroup
+constexpr int kStripPad = kStrip + kStrip / 8;
+
+// LDS slot of padded column e: one pad double per 8, so that both the
+// 4-columns-per-lane writes and the consecutive-column reads of the
+// epilogue spread over the banks.
+__device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -240,8 +246,8 @@ template <int N, typename TS>
 __global__ __launch_bounds__(kWaves * kWave) void moments_box(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max) {
-  __shared__ double sh[kWaves][N][kStrip];
+    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4) {
+  __shared__ double sh[kWaves][N][kStripPad];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int gw = blockIdx.x * kWaves + wv;
@@ -257,6 +263,18 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
   int cx[kV];
 #pragma unroll
   for (int v = 0; v < kV; ++v) cx[v] = min(max(xs + kV * lane + v, 0), W - 1);
+  // the lane's 4 columns as one aligned float4 when they are all inside the
+  // image (xs is a multiple of 4) and rows are 16-byte aligned
+  const bool v4 = vec4 && xs + kV * lane >= 0 && xs + kV * lane + kV <= W;
+  auto load4 = [&](const float* row, float (&q)[kV]) {
+    if (v4) {
+      const float4 t4 = *reinterpret_cast<const float4*>(row + xs + kV * lane);
+      q[0] = t4.x; q[1] = t4.y; q[2] = t4.z; q[3] = t4.w;
+    } else {
+#pragma unroll
+      for (int v = 0; v < kV; ++v) q[v] = row[cx[v]];
+    }
+  };
 
   double S[N][kV];
 #pragma unroll
@@ -266,9 +284,11 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
 
   for (int dy = -R; dy <= R; ++dy) {
     const float* row = img + (long long)min(max(y0 + dy, 0), H - 1) * pitch;
+    float q[kV];
+    load4(row, q);
 #pragma unroll
     for (int v = 0; v < kV; ++v) {
-      const double u = (double)row[cx[v]] - c;
+      const double u = (double)q[v] - c;
       double p = u;
 #pragma unroll
       for (int k = 0; k < N; ++k) {
@@ -283,10 +303,13 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
     if (y > y0) {
       const float* rin = img + (long long)min(y + R, H - 1) * pitch;
       const float* rout = img + (long long)max(y - R - 1, 0) * pitch;
+      float qi[kV], qo[kV];
+      load4(rin, qi);
+      load4(rout, qo);
 #pragma unroll
       for (int v = 0; v < kV; ++v) {
-        const double ui = (double)rin[cx[v]] - c;
-        const double uo = (double)rout[cx[v]] - c;
+        const double ui = (double)qi[v] - c;
+        const double uo = (double)qo[v] - c;
         double pi = ui, po = uo;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -305,17 +328,17 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
       double p3 = p2 + S[k][3];
       const double incl = wave_inclusive_scan(p3, lane);
       const double ex = incl - p3;
-      double* d = &sh[wv][k][kV * lane];
-      d[0] = ex + p0;
-      d[1] = ex + p1;
-      d[2] = ex + p2;
-      d[3] = incl;
+      double* d = sh[wv][k];
+      d[pidx(kV * lane + 0)] = ex + p0;
+      d[pidx(kV * lane + 1)] = ex + p1;
+      d[pidx(kV * lane + 2)] = ex + p2;
+      d[pidx(kV * lane + 3)] = incl;
     }
     wave_sync();
     auto sum_k = [&](int j, int k) -> double {
       const int e = g.Rpad + j;
-      const double hi = sh[wv][k][e + R];
-      const double lo = (e - R - 1 >= 0) ? sh[wv][k][e - R - 1] : 0.0;
+      const double hi = sh[wv][k][pidx(e + R)];
+      const double lo = (e - R - 1 >= 0) ? sh[wv][k][pidx(e - R - 1)] : 0.0;
       return (hi - lo) * inv_area;
     };
     epilogue_row<N, TS>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c, cond_max,
@@ -565,8 +588,9 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   const int waves = g.n_strips * g.n_segs;
   dim3 grid((waves + kWaves - 1) / kWaves);
   if (kind == 0) {
+    const int vec4 = (pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 16 == 0);
     hipLaunchKernelGGL((moments_box<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
-                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max);
+                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4);
   } else {
     const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
     const int tx = gauss_tile_tx(R, N);

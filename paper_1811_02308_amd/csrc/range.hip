@@ -50,6 +50,33 @@ __host__ __device__ constexpr double lam_split(int N, bool mixed) {
 __host__ __device__ constexpr double outside_limit(bool mixed) { return mixed ? 1.5 : 0.5; }
 constexpr double kSupport = 30.0;
 
+// exp(x) for x <= 0 (arguments here never exceed 0): Cody-Waite reduction
+// x = n ln2 + r, |r| <= ln2/2, with ln2 split in a high part exact to 32
+// bits and a low part; e^r by its Taylor series to r^13/13! (truncation
+// below 2^-55 relative); 2^n applied with ldexp. Results below the FP64
+// range flush to 0. A few ulp, i.e. far inside the FP64 path's tolerance.
+__device__ __forceinline__ double exp_neg(double x) {
+  if (x < -745.0) return 0.0;
+  const double n = rint(x * 1.4426950408889634074);
+  const double r = fma(n, -6.93147180369123816490e-01, x);
+  const double rr = fma(n, -1.90821492927058770002e-10, r);
+  double p = 1.0 / 6227020800.0;                    // 1/13!
+  p = fma(p, rr, 1.0 / 479001600.0);
+  p = fma(p, rr, 1.0 / 39916800.0);
+  p = fma(p, rr, 1.0 / 3628800.0);
+  p = fma(p, rr, 1.0 / 362880.0);
+  p = fma(p, rr, 1.0 / 40320.0);
+  p = fma(p, rr, 1.0 / 5040.0);
+  p = fma(p, rr, 1.0 / 720.0);
+  p = fma(p, rr, 1.0 / 120.0);
+  p = fma(p, rr, 1.0 / 24.0);
+  p = fma(p, rr, 1.0 / 6.0);
+  p = fma(p, rr, 0.5);
+  p = fma(p, rr, 1.0);
+  p = fma(p, rr, 1.0);
+  return ldexp(p, (int)n);
+}
+
 // 1/x from the hardware reciprocal estimate and two Newton steps (a few ulp;
 // used for parameters and the final ratio, never for exact quantities).
 __device__ __forceinline__ double rcp(double x) {
@@ -115,8 +142,8 @@ __global__ __launch_bounds__(256) void range_kernel(
     const double A = -sl * t0, B = sl * (1.0 - t0);
     const double dd = t0 - ts;
     const double s = lam * dd * dd;
-    const double E0 = exp(s - A * A);    // exp(-lam t0^2) * e^s
-    const double E1 = exp(s - B * B);    // exp(-lam (1-t0)^2) * e^s
+    const double E0 = exp_neg(s - A * A);    // exp(-lam t0^2) * e^s
+    const double E1 = exp_neg(s - B * B);    // exp(-lam (1-t0)^2) * e^s
     double diff;                          // (erf(B) - erf(A)) * e^s
     if (A <= 0.0 && B >= 0.0) {
       diff = 2.0 - erfcx(B) * E1 - erfcx(-A) * E0;
@@ -169,7 +196,7 @@ __global__ __launch_bounds__(256) void range_kernel(
       if (kMixed) {
         psi = (double)__expf((float)fmax(e, -80.0));
       } else {
-        psi = exp(e);
+        psi = exp_neg(e);
       }
       const double wpsi = span * gl.w[q] * psi;
       J0 += wpsi;
