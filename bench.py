@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--parity-pixels", type=int, default=600)
+    ap.add_argument("--serving-requests", type=int, default=0,
+                    help="also run the serving stream (p50/p99 at 3 offered loads) with this many requests")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -80,6 +82,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     abf.lib()
+    if args.workload.startswith("texture"):
+        return texture_bench(args)
     wl = workload(args.workload)
     f, th, sg = wl["f"], wl["theta"], wl["sigma"]
     H, W = f.shape
@@ -239,6 +243,70 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.serving_requests > 0:
+        from paper_1811_02308_amd.serve import bench as serve_bench
+        log("serving stream ...")
+        res["serving"] = serve_bench(n=args.serving_requests, warm=max(10, args.serving_requests // 10))
+    print(json.dumps(res), flush=True)
+
+
+def texture_bench(args):
+    """Texture workload: 32 RGB frames as 96 planes, 3 passes of
+    (sigma map, batched fast filter), one launch per stage per pass."""
+    import numpy as np
+    import torch
+
+    import paper_1811_02308_amd as abf
+    from synth import workload
+    wl = workload(args.workload)
+    frames = wl["frames"]
+    n, H, W = frames.shape
+    R, N, passes = wl["R"], wl["N"], wl["passes"]
+    sr = wl["sigma_rule"]
+    log(f"texture workload: {n} planes of {H}x{W}, box R={R}, N={N}, {passes} passes")
+    x = torch.from_numpy(frames).cuda()
+
+    def run(prec, steps, warmup):
+        for _ in range(warmup):
+            abf.texture_filter(x, passes, R, N, precision=prec, **sr)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            out = abf.texture_filter(x, passes, R, N, precision=prec, **sr)
+        e1.record()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
+
+    steps = max(1, min(args.steps, 5))
+    out_m, ms_m, dev_m = run("mixed", steps, 1)
+    out_d, ms_d, dev_d = run("fp64", steps, 1)
+    mpix = passes * n * H * W / 1e6
+    # parity of the last pass on sampled pixels of three planes: feed the
+    # oracle the GPU's own pass input and sigma map
+    import oracle
+    rng = np.random.default_rng(5)
+    errs = {"mixed": 0.0, "fp64": 0.0}
+    for prec in ("mixed", "fp64"):
+        prev = abf.texture_filter(x, passes - 1, R, N, precision=prec, **sr).float() if passes > 1 else x
+        sig = abf.sigma_local_std(prev, **sr)
+        last = abf.fast_strided(prev, sig, kernel="box", rho=R, N=N, precision=prec)
+        for c in (0, n // 2, n - 1):
+            ys, xs = rng.integers(0, H, 150), rng.integers(0, W, 150)
+            ref = oracle.fast_abf(prev[c].cpu().numpy(), None, sig[c].cpu().numpy(), "box", R, N,
+                                  pixels=(ys, xs))
+            got = last[c].cpu().numpy().astype(np.float64)[ys, xs]
+            errs[prec] = max(errs[prec], float(np.max(np.abs(got - ref))))
+    res = {"metric": METRIC, "value": round(mpix / (ms_m * 1e-3), 2), "unit": "Mpix/s", "n_gpus": 1,
+           "steps": steps, "warmup": 1, "ms_per_step": round(ms_m, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "planes": n, "h": H, "w": W, "kernel": "box", "rho": R,
+                      "N": N, "passes": passes, "precision": "mixed (FP64 arithmetic, FP32 stack and output)"},
+           "device_ms_per_step": round(dev_m, 4),
+           "fp64": {"value": round(mpix / (ms_d * 1e-3), 2), "ms_per_step": round(ms_d, 4),
+                    "max_abs_err_vs_oracle": errs["fp64"]},
+           "mixed_max_abs_err_vs_oracle": errs["mixed"], "roofline": None, "cpu_baseline": None}
     print(json.dumps(res), flush=True)
 
 

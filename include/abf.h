@@ -194,6 +194,38 @@ abf_status abf_fast_batched(const abf_request* reqs, int n, int precision,
                             unsigned flags, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/*
+ * abf_fast_strided -- abf_fast on n images of one shape and one parameter
+ * set laid out at a fixed stride: image z is img + z*image_stride (theta
+ * and sigma use the same stride), its output out + z*out_image_stride
+ * (elements of the output type). Each stage of Algorithm 1 is ONE launch
+ * whose grid covers all n images (e.g. the channels of a batch of colour
+ * frames, filtered channel by channel as in Sec. IV-C).
+ * workspace >= abf_strided_workspace_bytes(n, h, w, rho, N, precision):
+ * n moment stacks followed by one scratch area. n in [1, 65535].
+ */
+size_t abf_strided_workspace_bytes(int n, int h, int w, int rho, int N, int precision);
+abf_status abf_fast_strided(const float* img, const float* theta, const float* sigma, int n,
+                            int h, int w, long long pitch, long long image_stride,
+                            int kernel_kind, double sigma_s, int rho, int N, int precision,
+                            unsigned flags, void* out, long long out_pitch,
+                            long long out_image_stride, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
+/*
+ * abf_sigma_local_std -- a per-pixel range width from local contrast for
+ * texture filtering: sigma(i) = clamp(scale * sd(i), lo, hi), sd(i) the
+ * population standard deviation of f over the clamp-to-edge window
+ * [-radius, radius]^2 (FP64). The paper drives sigma from a local texture
+ * measure through an affine map (Sec. IV-C); this is the contrast rule of
+ * the texture benchmark. n images at image_stride / out_image_stride
+ * (elements). radius in [0, 32]; lo <= hi.
+ */
+abf_status abf_sigma_local_std(const float* img, int n, int h, int w, long long pitch,
+                               long long image_stride, int radius, double scale, double lo,
+                               double hi, float* out, long long out_pitch,
+                               long long out_image_stride, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

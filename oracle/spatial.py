@@ -117,3 +117,21 @@ def convolve_powers(u: np.ndarray, kind: str, R: int, sigma_s, N: int):
         out.append(g)
         uk = uk * u
     return out
+
+
+def local_std_sigma(f: np.ndarray, r: int = 4, scale: float = 3.0, lo: float = 5.0,
+                    hi: float = 80.0) -> np.ndarray:
+    """sigma(i) = clip(scale * sd(i), lo, hi), sd(i) the population standard
+    deviation of f over the clamp-to-edge window [-r, r]^2 of i (the contrast
+    rule of the texture benchmark; the paper's texture filter maps a local
+    texture measure to sigma, Sec. IV-C). FP64."""
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    out = np.empty(H * W)
+    yr, xr = ys.ravel(), xs.ravel()
+    step = 1 << 15
+    for s0 in range(0, H * W, step):
+        win = gather_windows(f, r, yr[s0:s0 + step], xr[s0:s0 + step])
+        out[s0:s0 + step] = np.clip(scale * win.std(axis=1), lo, hi)
+    return out.reshape(H, W)

@@ -18,7 +18,8 @@ import os
 
 __all__ = [
     "lib", "library_path", "fast", "bruteforce", "minmax", "moment_stack",
-    "range_from_stack", "fast_batched", "minmax_into_stack", "stack_moments", "workspace_bytes", "stack_bytes",
+    "range_from_stack", "fast_batched", "minmax_into_stack", "stack_moments",
+    "fast_strided", "sigma_local_std", "workspace_bytes", "stack_bytes",
     "stack_planes", "Request", "KERNELS", "PRECISIONS", "ABFError",
 ]
 
@@ -77,6 +78,9 @@ def lib():
         "abf_bruteforce": ([vp, vp, vp, i, i, ll, i, d, i, i, vp, ll, vp], i),
         "abf_batched_workspace_bytes": ([ctypes.POINTER(Request), i, i], sz),
         "abf_fast_batched": ([ctypes.POINTER(Request), i, i, u, vp, sz, vp], i),
+        "abf_strided_workspace_bytes": ([i, i, i, i, i, i], sz),
+        "abf_fast_strided": ([vp, vp, vp, i, i, i, ll, ll, i, d, i, i, i, u, vp, ll, ll, vp, sz, vp], i),
+        "abf_sigma_local_std": ([vp, i, i, i, ll, ll, i, d, d, d, vp, ll, ll, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -314,3 +318,82 @@ def fast_batched(items, precision="mixed", clamp=True, workspace=None, stream=No
                                 workspace.numel() if workspace is not None else 0, _stream(stream))
     _check(st, "abf_fast_batched")
     return outs
+
+
+def _batch3(t, name):
+    """A (n, h, w) float32 CUDA tensor with unit column stride -> (n, h, w, pitch, stride)."""
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise ABFError(f"{name} must be a float32 CUDA tensor")
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.stride(2) != 1:
+        raise ABFError(f"{name} must be (n, h, w) with unit column stride")
+    return t
+
+
+def fast_strided(img, sigma, theta=None, kernel="box", rho=3, N=5, sigma_s=0.0,
+                 precision="mixed", clamp=True, out=None, workspace=None, stream=None):
+    """abf_fast_strided: the fast filter on a stack of n images (n, h, w) of
+    one shape and parameter set, one launch per stage for the whole batch."""
+    torch = _torch()
+    img, sigma, theta = _batch3(img, "img"), _batch3(sigma, "sigma"), _batch3(theta, "theta")
+    n, h, w = img.shape
+    for o in (sigma, theta):
+        if o is not None and (o.shape != img.shape or o.stride() != img.stride()):
+            raise ABFError("theta/sigma must have the image batch's shape and strides")
+    p = _prec(precision)
+    if out is None:
+        out = torch.empty((n, h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+    need = lib().abf_strided_workspace_bytes(n, h, w, rho, N, p)
+    if workspace is None:
+        workspace = _alloc_bytes(need, img.device)
+    st = lib().abf_fast_strided(_ptr(img), _ptr(theta), _ptr(sigma), n, h, w, img.stride(1),
+                                img.stride(0), _kind(kernel), float(sigma_s), int(rho), int(N), p,
+                                FLAG_CLAMP if clamp else 0, _ptr(out), out.stride(1), out.stride(0),
+                                _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(st, "abf_fast_strided")
+    return out
+
+
+def sigma_local_std(img, radius=4, scale=3.0, lo=5.0, hi=80.0, out=None, stream=None):
+    """abf_sigma_local_std: sigma = clamp(scale * local std over (2r+1)^2, lo, hi)."""
+    torch = _torch()
+    img = _batch3(img, "img")
+    n, h, w = img.shape
+    if out is None:
+        out = torch.empty((n, h, w), dtype=torch.float32, device=img.device)
+    st = lib().abf_sigma_local_std(_ptr(img), n, h, w, img.stride(1), img.stride(0), int(radius),
+                                   float(scale), float(lo), float(hi), _ptr(out), out.stride(1),
+                                   out.stride(0), _stream(stream))
+    _check(st, "abf_sigma_local_std")
+    return out
+
+
+def texture_filter(frames, passes=3, rho=8, N=6, radius=4, scale=3.0, lo=5.0, hi=80.0,
+                   precision="mixed", stream=None):
+    """Iterated adaptive filtering of a batch of planar channel-images
+    (n, h, w) as in the texture-removal use (Sec. IV-C: the filter applied
+    repeatedly, channel by channel): each pass recomputes sigma from the
+    current input's local contrast (abf_sigma_local_std) and filters the
+    whole batch with one abf_fast_strided call (theta = f, box kernel).
+    Returns the output of the last pass (float32 for 'mixed')."""
+    torch = _torch()
+    x = _batch3(frames, "frames")
+    n, h, w = x.shape
+    p = _prec(precision)
+    ws = _alloc_bytes(lib().abf_strided_workspace_bytes(n, h, w, rho, N, p), x.device)
+    sig = torch.empty_like(x)
+    outs = [torch.empty((n, h, w), dtype=torch.float64 if p == 0 else torch.float32,
+                        device=x.device) for _ in range(2)]
+    cur = x
+    for i in range(passes):
+        sigma_local_std(cur if cur.dtype == torch.float32 else cur.float(), radius, scale, lo, hi,
+                        out=sig, stream=stream)
+        src = cur if cur.dtype == torch.float32 else cur.float()
+        fast_strided(src, sig, kernel="box", rho=rho, N=N, precision=precision,
+                     out=outs[i % 2], workspace=ws, stream=stream)
+        cur = outs[i % 2]
+    return cur

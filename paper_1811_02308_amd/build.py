@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabf.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "minmax.hip", "moments.hip", "range.hip", "brute.hip"]
+SOURCES = ["api.cpp", "minmax.hip", "moments.hip", "range.hip", "brute.hip", "sigma.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

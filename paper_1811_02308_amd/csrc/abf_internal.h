@@ -58,24 +58,49 @@ struct ShiftedLegTable {
   }
 };
 
+// A batch of images of one shape and one parameter set, laid out at fixed
+// strides: image z uses img + z*img (elements; also theta and sigma), the
+// stack at byte offset z*stack, and out + z*out (elements). Kernels take the
+// image index from the last grid dimension, so a whole batch is one launch
+// per stage. n = 1 with zero strides is a single image.
+struct Batch {
+  int n = 1;
+  long long img = 0;
+  long long stack = 0;
+  long long out = 0;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ T* byte_offset(T* p, long long bytes) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<void*>(static_cast<const void*>(p))) + bytes);
+}
+
 // Launchers (all asynchronous on `stream`; return hipGetLastError()).
+// alpha/beta of image z are at byte offset z*b.stack (b.stack = 0 for n = 1).
 hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rho,
                          float* alpha, float* beta, long long out_pitch,
-                         void* scratch, hipStream_t stream);
+                         void* scratch, hipStream_t stream, const Batch& b = Batch());
 
 // prec: 0 = FP64 stack, 1 = FP32 stack. N >= 1. The alpha/beta planes of the
 // stack must already hold the window bounds.
 hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           int kernel_kind, double sigma_s, int rho, int N, int prec,
                           const float* alpha, const float* beta, long long sp,
-                          void* mom, long long plane_elems, hipStream_t stream);
+                          void* mom, long long plane_elems, hipStream_t stream,
+                          const Batch& b = Batch());
 
 hipError_t launch_range(const float* alpha, const float* beta, long long sp,
                         const void* mom, long long plane_elems,
                         const float* theta_or_img, long long tpitch,
                         const float* sigma, long long spitch, int h, int w,
                         int N, int prec, unsigned flags, void* out, long long opitch,
-                        hipStream_t stream);
+                        hipStream_t stream, const Batch& b = Batch());
+
+// sigma(i) = clamp(scale * std of f over the (2r+1)^2 clamp-to-edge window,
+// lo, hi), population standard deviation, FP64.
+hipError_t launch_sigma_std(const float* img, long long pitch, int h, int w, int r,
+                            double scale, double lo, double hi, float* out, long long opitch,
+                            hipStream_t stream, const Batch& b = Batch());
 
 hipError_t launch_brute(const float* img, const float* theta, const float* sigma,
                         long long pitch, int h, int w, int kernel_kind, double sigma_s,

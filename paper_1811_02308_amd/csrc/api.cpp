@@ -250,4 +250,68 @@ abf_status abf_fast_batched(const abf_request* reqs, int n, int precision, unsig
   return ABF_OK;
 }
 
+size_t abf_strided_workspace_bytes(int n, int h, int w, int rho, int N, int precision) {
+  if (n < 1 || h < 1 || w < 1 || N < 0) return 0;
+  return (size_t)n * abf_stack_bytes(h, w, N, precision) + abf_scratch_bytes(h, w, rho);
+}
+
+abf_status abf_fast_strided(const float* img, const float* theta, const float* sigma, int n,
+                            int h, int w, long long pitch, long long image_stride,
+                            int kernel_kind, double sigma_s, int rho, int N, int precision,
+                            unsigned flags, void* out, long long out_pitch,
+                            long long out_image_stride, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  if (!img || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0 || N < 0 ||
+      !prec_ok(precision) || !kind_ok(kernel_kind) || n < 1 || n > 65535 ||
+      (n > 1 && (image_stride < pitch * (long long)(h - 1) + w ||
+                 out_image_stride < out_pitch * (long long)(h - 1) + w)) ||
+      !std::isfinite(sigma_s))
+    return ABF_E_INVALID;
+  if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (!workspace || !aligned(workspace) ||
+      workspace_bytes < abf_strided_workspace_bytes(n, h, w, rho, N, precision))
+    return ABF_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t sb = abf_stack_bytes(h, w, N, precision);
+  const long long sp = abf_stack_pitch(w);
+  char* base = static_cast<char*>(workspace);
+  void* scratch = base + (size_t)n * sb;
+  abf::Batch b;
+  b.n = n;
+  b.img = n > 1 ? image_stride : 0;
+  b.stack = n > 1 ? (long long)sb : 0;
+  b.out = n > 1 ? out_image_stride : 0;
+  float* alpha = reinterpret_cast<float*>(base);
+  float* beta = reinterpret_cast<float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
+  void* mom = base + abf_stack_plane_offset(h, w, N, precision, 2);
+  const int pc = precision == ABF_PREC_FP64 ? 0 : 1;
+  hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, scratch, s, b);
+  if (e != hipSuccess) return ABF_E_HIP;
+  if (N > 0) {
+    e = abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, pc, alpha, beta, sp,
+                            mom, sp * h, s, b);
+    if (e != hipSuccess) return ABF_E_HIP;
+  }
+  return hip_status(abf::launch_range(alpha, beta, sp, mom, sp * h, theta ? theta : img, pitch,
+                                      sigma, pitch, h, w, N, pc, flags, out, out_pitch, s, b));
+}
+
+abf_status abf_sigma_local_std(const float* img, int n, int h, int w, long long pitch,
+                               long long image_stride, int radius, double scale, double lo,
+                               double hi, float* out, long long out_pitch,
+                               long long out_image_stride, void* stream) {
+  if (!img || !out || !shape_ok(h, w, pitch) || out_pitch < w || radius < 0 || n < 1 ||
+      n > 65535 || !(lo <= hi) || !std::isfinite(scale) ||
+      (n > 1 && (image_stride < pitch * (long long)(h - 1) + w ||
+                 out_image_stride < out_pitch * (long long)(h - 1) + w)))
+    return ABF_E_INVALID;
+  if (radius > 32) return ABF_E_UNSUPPORTED;
+  abf::Batch b;
+  b.n = n;
+  b.img = n > 1 ? image_stride : 0;
+  b.out = n > 1 ? out_image_stride : 0;
+  return hip_status(abf::launch_sigma_std(img, pitch, h, w, radius, scale, lo, hi, out, out_pitch,
+                                          static_cast<hipStream_t>(stream), b));
+}
+
 }  // extern "C"

@@ -163,8 +163,11 @@ __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&m
 
 __global__ __launch_bounds__(kThreads) void minmax_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
-    float* __restrict__ out_a, float* __restrict__ out_b, long long op) {
+    float* __restrict__ out_a, float* __restrict__ out_b, long long op, Batch bt) {
   extern __shared__ float lds[];
+  img += blockIdx.z * bt.img;
+  out_a = byte_offset(out_a, blockIdx.z * bt.stack);
+  out_b = byte_offset(out_b, blockIdx.z * bt.stack);
   // LDS row strides: odd for the padded tile and kMTX + 1 for the
   // horizontal result, so that threads walking different rows hit
   // different banks
@@ -221,34 +224,39 @@ int rows_per_block(int R) {
 
 hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rho,
                          float* alpha, float* beta, long long out_pitch,
-                         void* scratch, hipStream_t stream) {
-  // The window clipped to the image is the same for any radius >= dim - 1.
-  const int Rh = rho < w - 1 ? rho : w - 1;
-  const int Rv = rho < h - 1 ? rho : h - 1;
+                         void* scratch, hipStream_t stream, const Batch& b) {
   if (rho <= kTileRMax) {
     // clamping of the padded tile makes any radius exact; use rho itself
-    dim3 grid((w + kMTX - 1) / kMTX, (h + kMTY - 1) / kMTY);
+    dim3 grid((w + kMTX - 1) / kMTX, (h + kMTY - 1) / kMTY, b.n);
     const int EX = kMTX + 2 * rho, EY = kMTY + 2 * rho, XS = EX | 1;
     const size_t lds = (size_t)((EY * XS + 1) & ~1) * sizeof(float) + (size_t)EY * kHS * sizeof(float2);
     hipLaunchKernelGGL(minmax_tile, grid, dim3(kThreads), lds, stream, img, pitch, h, w, rho,
-                       alpha, beta, out_pitch);
+                       alpha, beta, out_pitch, b);
     return hipGetLastError();
   }
+  // The window clipped to the image is the same for any radius >= dim - 1.
+  const int Rh = rho < w - 1 ? rho : w - 1;
+  const int Rv = rho < h - 1 ? rho : h - 1;
   const long long tp = ((long long)h + 63) / 64 * 64;   // pitch of transposed rows
   float2* t = static_cast<float2*>(scratch);
-  {
-    const int ROWS = rows_per_block(Rh);
-    dim3 grid((w + kTX - 1) / kTX, (h + ROWS - 1) / ROWS);
-    size_t lds = (size_t)ROWS * (2 * kTX + 2 * Rh) * sizeof(float2);
-    hipLaunchKernelGGL(vh_rows<true>, grid, dim3(kThreads), lds, stream,
-                       img, pitch, h, w, Rh, ROWS, t, tp, nullptr, nullptr, 0LL);
-  }
-  {
-    const int ROWS = rows_per_block(Rv);
-    dim3 grid((h + kTX - 1) / kTX, (w + ROWS - 1) / ROWS);
-    size_t lds = (size_t)ROWS * (2 * kTX + 2 * Rv) * sizeof(float2);
-    hipLaunchKernelGGL(vh_rows<false>, grid, dim3(kThreads), lds, stream,
-                       (const void*)t, tp, w, h, Rv, ROWS, nullptr, 0LL, alpha, beta, out_pitch);
+  for (int z = 0; z < b.n; ++z) {    // large radii: one image at a time through the scratch
+    const float* im = img + z * b.img;
+    float* az = byte_offset(alpha, z * b.stack);
+    float* bz = byte_offset(beta, z * b.stack);
+    {
+      const int ROWS = rows_per_block(Rh);
+      dim3 grid((w + kTX - 1) / kTX, (h + ROWS - 1) / ROWS);
+      size_t lds = (size_t)ROWS * (2 * kTX + 2 * Rh) * sizeof(float2);
+      hipLaunchKernelGGL(vh_rows<true>, grid, dim3(kThreads), lds, stream,
+                         im, pitch, h, w, Rh, ROWS, t, tp, nullptr, nullptr, 0LL);
+    }
+    {
+      const int ROWS = rows_per_block(Rv);
+      dim3 grid((h + kTX - 1) / kTX, (w + ROWS - 1) / ROWS);
+      size_t lds = (size_t)ROWS * (2 * kTX + 2 * Rv) * sizeof(float2);
+      hipLaunchKernelGGL(vh_rows<false>, grid, dim3(kThreads), lds, stream,
+                         (const void*)t, tp, w, h, Rv, ROWS, nullptr, 0LL, az, bz, out_pitch);
+    }
   }
   return hipGetLastError();
 }

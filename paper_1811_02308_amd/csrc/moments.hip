@@ -246,8 +246,12 @@ template <int N, typename TS>
 __global__ __launch_bounds__(kWaves * kWave) void moments_box(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4) {
+    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4, Batch bt) {
   __shared__ double sh[kWaves][N][kStripPad];
+  img += blockIdx.y * bt.img;
+  alpha = byte_offset(alpha, blockIdx.y * bt.stack);
+  beta = byte_offset(beta, blockIdx.y * bt.stack);
+  mom = byte_offset(mom, blockIdx.y * bt.stack);
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int gw = blockIdx.x * kWaves + wv;
@@ -432,8 +436,12 @@ template <int N, typename TS>
 __global__ __launch_bounds__(256) void moments_gauss_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R, int TX, double inv2s2,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, double cond_max) {
+    TS* __restrict__ mom, long long plane, double cond_max, Batch bt) {
   extern __shared__ double vsum[];            // [N][kTY][E]
+  img += blockIdx.z * bt.img;
+  alpha = byte_offset(alpha, blockIdx.z * bt.stack);
+  beta = byte_offset(beta, blockIdx.z * bt.stack);
+  mom = byte_offset(mom, blockIdx.z * bt.stack);
   __shared__ double wts[2 * kRhoMax + 1];
   __shared__ double origin;
   const int E = TX + 2 * R;
@@ -580,41 +588,47 @@ StripGeom make_geom(int H, int W, int R, int target_waves) {
 template <int N, typename TS>
 hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int kind,
                             double sigma_s, int R, const float* alpha, const float* beta,
-                            long long sp, TS* mom, long long plane, hipStream_t stream) {
-  const StripGeom g = make_geom(h, w, R, 2560);
+                            long long sp, TS* mom, long long plane, hipStream_t stream,
+                            const Batch& b) {
+  const StripGeom g = make_geom(h, w, R, 2560 / (b.n > 0 ? b.n : 1) + 1);
   // largest tolerated shift amplification: FP64 stack keeps ~1e-8 relative
   // headroom; the FP32 stack only needs to stay below its own rounding
   const double cond_max = sizeof(TS) == 8 ? 1e8 : 1e12;
   const int waves = g.n_strips * g.n_segs;
-  dim3 grid((waves + kWaves - 1) / kWaves);
   if (kind == 0) {
-    const int vec4 = (pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 16 == 0);
+    dim3 grid((waves + kWaves - 1) / kWaves, b.n);
+    const int vec4 = (pitch % 4 == 0) && (b.img % 4 == 0) &&
+                     (reinterpret_cast<uintptr_t>(img) % 16 == 0);
     hipLaunchKernelGGL((moments_box<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
-                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4);
-  } else {
-    const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
-    const int tx = gauss_tile_tx(R, N);
-    if (tx > 0) {
-      dim3 tg((w + tx - 1) / tx, (h + kTY - 1) / kTY);
-      const size_t lds = (size_t)N * kTY * (tx + 2 * R) * sizeof(double);
-      hipLaunchKernelGGL((moments_gauss_tile<N, TS>), tg, dim3(256), lds, stream, img, pitch, h,
-                         w, R, tx, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, cond_max);
-      return hipGetLastError();
-    }
-    hipLaunchKernelGGL((moments_gauss<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
-                       img, pitch, h, w, R, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, g,
-                       cond_max);
+                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b);
+    return hipGetLastError();
   }
+  const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
+  const int tx = gauss_tile_tx(R, N);
+  if (tx > 0) {
+    dim3 tg((w + tx - 1) / tx, (h + kTY - 1) / kTY, b.n);
+    const size_t lds = (size_t)N * kTY * (tx + 2 * R) * sizeof(double);
+    hipLaunchKernelGGL((moments_gauss_tile<N, TS>), tg, dim3(256), lds, stream, img, pitch, h,
+                       w, R, tx, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, cond_max, b);
+    return hipGetLastError();
+  }
+  dim3 grid((waves + kWaves - 1) / kWaves);
+  for (int z = 0; z < b.n; ++z)
+    hipLaunchKernelGGL((moments_gauss<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
+                       img + z * b.img, pitch, h, w, R, 1.0 / (2.0 * s * s),
+                       byte_offset(alpha, z * b.stack), byte_offset(beta, z * b.stack), sp,
+                       byte_offset(mom, z * b.stack), plane, g, cond_max);
   return hipGetLastError();
 }
 
 template <typename TS>
 hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, int kind,
                       double sigma_s, int R, const float* alpha, const float* beta,
-                      long long sp, TS* mom, long long plane, hipStream_t stream) {
+                      long long sp, TS* mom, long long plane, hipStream_t stream,
+                      const Batch& b) {
   switch (N) {
 #define ABF_CASE(n) \
-  case n: return launch_moments_t<n, TS>(img, pitch, h, w, kind, sigma_s, R, alpha, beta, sp, mom, plane, stream);
+  case n: return launch_moments_t<n, TS>(img, pitch, h, w, kind, sigma_s, R, alpha, beta, sp, mom, plane, stream, b);
     ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6) ABF_CASE(7) ABF_CASE(8)
 #undef ABF_CASE
     default: return hipErrorInvalidValue;
@@ -626,12 +640,12 @@ hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, in
 hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           int kernel_kind, double sigma_s, int rho, int N, int prec,
                           const float* alpha, const float* beta, long long sp,
-                          void* mom, long long plane_elems, hipStream_t stream) {
+                          void* mom, long long plane_elems, hipStream_t stream, const Batch& b) {
   if (prec == 0)
     return dispatch_n<double>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
-                              static_cast<double*>(mom), plane_elems, stream);
+                              static_cast<double*>(mom), plane_elems, stream, b);
   return dispatch_n<float>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
-                           static_cast<float*>(mom), plane_elems, stream);
+                           static_cast<float*>(mom), plane_elems, stream, b);
 }
 
 }  // namespace abf

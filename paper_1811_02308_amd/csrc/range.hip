@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void range_kernel(
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
     const TS* __restrict__ mom, long long plane, const float* __restrict__ theta,
     long long tpitch, const float* __restrict__ sigma, long long spitch, int H, int W,
-    unsigned flags, TO* __restrict__ out, long long opitch, GLArgs gl) {
+    unsigned flags, TO* __restrict__ out, long long opitch, GLArgs gl, Batch bt) {
   constexpr ShiftedLegTable SL{};
   constexpr LegTable LT{};
   // mixed path: 12-node rule and single-precision exponentials for the
@@ -108,6 +108,15 @@ __global__ __launch_bounds__(256) void range_kernel(
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (x >= W || y >= H) return;
+  {
+    const long long z = blockIdx.z;
+    alpha = byte_offset(alpha, z * bt.stack);
+    beta = byte_offset(beta, z * bt.stack);
+    mom = byte_offset(mom, z * bt.stack);
+    theta += z * bt.img;
+    sigma += z * bt.img;
+    out += z * bt.out;
+  }
   const long long idx = (long long)y * sp + x;
   const float a = alpha[idx], b = beta[idx];
   TO* o = out + (long long)y * opitch + x;
@@ -216,17 +225,17 @@ template <int N, typename TS, typename TO>
 hipError_t launch_t(const float* alpha, const float* beta, long long sp, const void* mom,
                     long long plane, const float* theta, long long tpitch, const float* sigma,
                     long long spitch, int h, int w, unsigned flags, void* out, long long opitch,
-                    hipStream_t stream) {
+                    hipStream_t stream, const Batch& b) {
   GLArgs gl;
   const GLRule& r = gl_rule(sizeof(TO) == 4 ? kGLNodesMixed : kGLNodes);
   for (int q = 0; q < kGLNodes; ++q) {
     gl.t[q] = r.t[q];
     gl.w[q] = r.w[q];
   }
-  dim3 grid((w + 63) / 64, (h + 3) / 4);
+  dim3 grid((w + 63) / 64, (h + 3) / 4, b.n);
   hipLaunchKernelGGL((range_kernel<N, TS, TO>), grid, dim3(256), 0, stream, alpha, beta, sp,
                      static_cast<const TS*>(mom), plane, theta, tpitch, sigma, spitch, h, w,
-                     flags, static_cast<TO*>(out), opitch, gl);
+                     flags, static_cast<TO*>(out), opitch, gl, b);
   return hipGetLastError();
 }
 
@@ -234,12 +243,12 @@ template <typename TS, typename TO>
 hipError_t dispatch(int N, const float* alpha, const float* beta, long long sp, const void* mom,
                     long long plane, const float* theta, long long tpitch, const float* sigma,
                     long long spitch, int h, int w, unsigned flags, void* out, long long opitch,
-                    hipStream_t stream) {
+                    hipStream_t stream, const Batch& b) {
   switch (N) {
 #define ABF_CASE(n)                                                                           \
   case n:                                                                                     \
     return launch_t<n, TS, TO>(alpha, beta, sp, mom, plane, theta, tpitch, sigma, spitch, h, \
-                               w, flags, out, opitch, stream);
+                               w, flags, out, opitch, stream, b);
     ABF_CASE(0) ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6)
     ABF_CASE(7) ABF_CASE(8)
 #undef ABF_CASE
@@ -255,12 +264,12 @@ hipError_t launch_range(const float* alpha, const float* beta, long long sp,
                         const float* theta_or_img, long long tpitch,
                         const float* sigma, long long spitch, int h, int w,
                         int N, int prec, unsigned flags, void* out, long long opitch,
-                        hipStream_t stream) {
+                        hipStream_t stream, const Batch& b) {
   if (prec == 0)
     return dispatch<double, double>(N, alpha, beta, sp, mom, plane_elems, theta_or_img, tpitch,
-                                    sigma, spitch, h, w, flags, out, opitch, stream);
+                                    sigma, spitch, h, w, flags, out, opitch, stream, b);
   return dispatch<float, float>(N, alpha, beta, sp, mom, plane_elems, theta_or_img, tpitch,
-                                sigma, spitch, h, w, flags, out, opitch, stream);
+                                sigma, spitch, h, w, flags, out, opitch, stream, b);
 }
 
 }  // namespace abf

@@ -187,6 +187,17 @@ for _R in (5, 20):
             lambda seed=1003, size=4096, R=_R, N=_N: _voronoi(seed, size, R, N))
 
 
+def _texture(seed: int = 1005, n_frames: int = 32, h: int = 1080, w: int = 1920):
+    frames = texture_frames(seed, n_frames, h, w)
+    return dict(frames=frames.reshape(n_frames * 3, h, w), kernel="box", sigma_s=0.0, R=8, N=6,
+                passes=3, sigma_rule=dict(radius=4, scale=3.0, lo=5.0, hi=80.0))
+
+
+# 32 RGB 1920 x 1080 frames of textured Voronoi regions, filtered channel by
+# channel (96 planes), box R=8, N=6, 3 passes, sigma = clip(3 * std_9x9, 5, 80)
+WORKLOADS["texture1080_box8_n6"] = _texture
+
+
 def workload(name: str, **kw):
     """Return the named workload dict (see ``WORKLOADS``)."""
     return WORKLOADS[name](**kw)

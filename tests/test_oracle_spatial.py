@@ -94,3 +94,13 @@ def test_legendre_moments_equal_ell_times_mu():
     assert np.allclose(am, mu @ ell.T, atol=1e-9)
     assert np.allclose(am[:, 0], 1.0, atol=1e-15)
     assert np.all(np.abs(am) <= 1 + 1e-12)      # |P_k| <= 1 on [-1, 1]
+
+
+def test_local_std_sigma_matches_library_filter():
+    from scipy.ndimage import generic_filter
+    from oracle.spatial import local_std_sigma
+    rng = np.random.default_rng(3)
+    f = (rng.random((13, 17)) * 120).astype(np.float32)
+    for r in (0, 1, 4):
+        ref = np.clip(3.0 * generic_filter(f.astype(np.float64), np.std, size=2 * r + 1, mode="nearest"), 5, 80)
+        assert np.allclose(local_std_sigma(f, r), ref, rtol=1e-12, atol=1e-12)

@@ -1,0 +1,112 @@
+"""Serving loop: admission, memory accounting, ordering, failures and stack
+reuse on a CPU fake executor (virtual clock), plus a GPU test that every
+result served in a mixed stream equals the same request run alone."""
+import numpy as np
+import pytest
+
+from paper_1811_02308_amd.serve import FakeExecutor, Request, Server, make_requests, summarize
+
+
+def _reqs(n=40, seed=0, rate=2000.0, same_image_every=0):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        h, w = int(rng.choice([16, 32, 64])), int(rng.choice([16, 48]))
+        img_id = ("shared", h, w) if same_image_every and i % same_image_every == 0 else ("img", i)
+        f = np.full((h, w), float(i), dtype=np.float32)
+        out.append(Request(id=i, t_arrival=t, image_id=img_id, f=f,
+                           sigma=np.ones((h, w), np.float32), rho=3, N=int(rng.choice([5, 8]))))
+    return out
+
+
+def test_all_complete_fifo_and_budget():
+    reqs = _reqs(60)
+    ex = FakeExecutor(n_slots=3, us_per_px=50.0)
+    budget = 200_000
+    srv = Server(ex, budget)
+    res = srv.run(reqs, realtime=False)
+    assert all(r.ok for r in res)
+    for r, q in zip(res, reqs):
+        assert np.array_equal(r.out, q.f)
+        assert r.t_done >= r.t_admit >= r.t_arrival
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i].t_arrival)
+    assert ex.launched == [reqs[i].id for i in order]          # FIFO admission
+    assert srv.max_in_use <= budget
+
+
+def test_continuous_admission_overlaps_work():
+    f = np.zeros((64, 64), np.float32)
+    reqs = [Request(id=0, t_arrival=0.0, image_id=0, f=f, sigma=f + 1),
+            Request(id=1, t_arrival=0.001, image_id=1, f=f, sigma=f + 1)]
+    ex = FakeExecutor(n_slots=2, us_per_px=1.0)                 # 4 ms per request
+    res = Server(ex, 10**9).run(reqs, realtime=False)
+    assert res[1].t_admit < res[0].t_done                      # admitted while 0 runs
+    assert abs(res[0].latency - 64 * 64 * 1e-6) < 1e-12
+
+
+def test_failures_do_not_stop_the_loop():
+    reqs = _reqs(20, seed=3)
+    ex = FakeExecutor(n_slots=2, us_per_px=5.0, fail_ids={4, 11}, fail_at_result={7})
+    res = Server(ex, 10**9).run(reqs, realtime=False)
+    bad = {r.id for r in res if not r.ok}
+    assert bad == {4, 7, 11}
+    assert all(r.ok for r in res if r.id not in bad)
+
+
+def test_oversized_request_rejected():
+    f = np.zeros((100, 100), np.float32)
+    reqs = [Request(id=0, t_arrival=0.0, image_id=0, f=f, sigma=f),
+            Request(id=1, t_arrival=0.0, image_id=1, f=f[:10, :10], sigma=f[:10, :10])]
+    res = Server(FakeExecutor(), 20_000).run(reqs, realtime=False)
+    assert not res[0].ok and "budget" in res[0].error
+    assert res[1].ok
+
+
+def test_stack_reuse_and_eviction_accounting():
+    reqs = _reqs(30, seed=5, same_image_every=3)
+    # force identical parameters for the shared image so the stack key repeats
+    for r in reqs:
+        if r.image_id[0] == "shared":
+            r.N = 5
+            r.f = np.full(r.f.shape, 7.0, np.float32)
+    ex = FakeExecutor(n_slots=2, us_per_px=2.0)
+    srv = Server(ex, 400_000)
+    res = srv.run(reqs, realtime=False)
+    assert all(r.ok for r in res)
+    hits = [r for r in res if r.stack_hit]
+    assert len(hits) >= 2
+    assert srv.max_in_use <= 400_000
+    s = summarize(res)
+    assert s["ok"] == 30 and s["p99_ms"] >= s["p50_ms"] >= 0
+
+
+def test_request_stream_generator_shapes():
+    reqs = make_requests(1004, 12, rate=100.0, scale=1 / 16)
+    assert all(r.f.shape[0] in (16, 32, 64, 128) for r in reqs)
+    assert all(r.rho in (3, 5, 10, 20) and r.N in (5, 6, 8) for r in reqs)
+    assert all(b.t_arrival >= a.t_arrival for a, b in zip(reqs, reqs[1:]))
+
+
+@pytest.mark.gpu
+def test_gpu_mix_equals_alone():
+    import torch
+    import paper_1811_02308_amd as abf
+    from paper_1811_02308_amd.serve import GPUExecutor
+    reqs = make_requests(2024, 40, rate=2000.0, scale=1 / 8)
+    # repeat a few images with new sigma maps so that stacks are reused
+    for r in reqs[20:30]:
+        src = reqs[r.id - 20]
+        r.image_id, r.f, r.kernel, r.rho, r.N, r.sigma_s = (src.image_id, src.f, src.kernel,
+                                                            src.rho, src.N, src.sigma_s)
+        r.sigma = r.sigma[: r.f.shape[0], : r.f.shape[1]] if r.sigma.shape == r.f.shape else \
+            np.full(r.f.shape, 17.0, np.float32)
+    srv = Server(GPUExecutor(n_slots=4), 2 << 30)
+    res = srv.run(reqs)
+    assert all(r.ok for r in res), [r.error for r in res if not r.ok]
+    assert any(r.stack_hit for r in res)
+    for q, r in zip(reqs, res):
+        alone = abf.fast(torch.from_numpy(q.f).cuda(), torch.from_numpy(np.ascontiguousarray(q.sigma)).cuda(),
+                         kernel=q.kernel, rho=q.rho, N=q.N, sigma_s=q.sigma_s).cpu().numpy()
+        assert np.array_equal(r.out, alone), q.id
