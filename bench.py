@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--parity-pixels", type=int, default=600)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 256 MiB device-to-device copy (counter calibration for profiles)")
     ap.add_argument("--serving-requests", type=int, default=0,
                     help="also run the serving stream (p50/p99 at 3 offered loads) with this many requests")
     args = ap.parse_args()
@@ -82,6 +84,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     abf.lib()
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
     if args.workload.startswith("texture"):
         return texture_bench(args)
     wl = workload(args.workload)

@@ -167,6 +167,72 @@ __device__ __forceinline__ void direct_legendre(const float* __restrict__ img, l
   }
 }
 
+// The same sum evaluated by one lane for its own pixel (used when most of a
+// wave's pixels need the recompute, so that all lanes work at once).
+template <int N>
+__device__ __forceinline__ void direct_legendre_lane(const float* __restrict__ img, long long pitch,
+                                                     int H, int W, int R, int y, int x, float a,
+                                                     float b, const double* __restrict__ wts,
+                                                     double norm, double (&acc)[N + 1]) {
+  const double mid = 0.5 * ((double)a + (double)b);
+  const double ih = 2.0 / ((double)b - (double)a);
+#pragma unroll
+  for (int k = 1; k <= N; ++k) acc[k] = 0.0;
+  for (int dy = -R; dy <= R; ++dy) {
+    const float* row = img + (long long)min(max(y + dy, 0), H - 1) * pitch;
+    const double wy = wts ? wts[dy + R] : 1.0;
+    for (int dx = -R; dx <= R; ++dx) {
+      const double z = ((double)row[min(max(x + dx, 0), W - 1)] - mid) * ih;
+      const double wt = wts ? wy * wts[dx + R] : 1.0;
+      double p0 = 1.0, p1 = z;
+      acc[1] = fma(wt, p1, acc[1]);
+#pragma unroll
+      for (int k = 2; k <= N; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        acc[k] = fma(wt, p2, acc[k]);
+        p0 = p1;
+        p1 = p2;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 1; k <= N; ++k) acc[k] *= norm;
+}
+
+// Recompute the flagged pixels of a wave: one pixel at a time by the whole
+// wave when few are flagged, every flagged lane its own pixel when many are.
+template <int N, typename TS>
+__device__ __forceinline__ void recompute_flagged(unsigned long long mask, bool mine, int y, int x,
+                                                  float a, float b, const float* __restrict__ img,
+                                                  long long pitch, int H, int W, int R,
+                                                  const double* __restrict__ wts, double norm,
+                                                  TS* __restrict__ mom, long long plane,
+                                                  long long sp, int lane) {
+  if (__popcll(mask) > 24) {
+    if (mine) {
+      double acc[N + 1];
+      direct_legendre_lane<N>(img, pitch, H, W, R, y, x, a, b, wts, norm, acc);
+      const long long il = (long long)y * sp + x;
+#pragma unroll
+      for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
+    }
+    return;
+  }
+  while (mask) {
+    const int l = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    const int yl = __shfl(y, l, kWave), xl = __shfl(x, l, kWave);
+    const float al = __shfl(a, l, kWave), bl = __shfl(b, l, kWave);
+    double acc[N + 1];
+    direct_legendre<N>(img, pitch, H, W, R, yl, xl, al, bl, wts, norm, lane, acc);
+    if (lane == 0) {
+      const long long il = (long long)yl * sp + xl;
+#pragma unroll
+      for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
+    }
+  }
+}
+
 // Epilogue for one output row of a wave: lanes take consecutive output
 // columns j0 + lane; `sum_k(j, k)` returns the normalised window moment of
 // u^(k+1) for strip column j. Ill-conditioned pixels are recomputed by the
@@ -199,20 +265,10 @@ __device__ __forceinline__ void epilogue_row(SumFn sum_k, int y, int xo, int O, 
         for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
       }
     }
-    unsigned long long mask = __ballot(valid && bad);
-    while (mask) {
-      const int l = __ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      const int xl = __shfl(x, l, kWave);
-      const float al = __shfl(a, l, kWave), bl = __shfl(b, l, kWave);
-      double acc[N + 1];
-      direct_legendre<N>(img, pitch, H, W, R, y, xl, al, bl, wts, norm, lane, acc);
-      if (lane == 0) {
-        const long long il = (long long)y * sp + xl;
-#pragma unroll
-        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
-      }
-    }
+    const unsigned long long mask = __ballot(valid && bad);
+    if (mask)
+      recompute_flagged<N, TS>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm, mom,
+                               plane, sp, lane);
   }
 }
 
@@ -543,20 +599,10 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
         for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
       }
     }
-    unsigned long long mask = __ballot(valid && bad);
-    while (mask) {
-      const int l = __ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      const int yl = __shfl(y, l, kWave), xl2 = __shfl(x, l, kWave);
-      const float al = __shfl(a, l, kWave), bl = __shfl(b, l, kWave);
-      double acc[N + 1];
-      direct_legendre<N>(img, pitch, H, W, R, yl, xl2, al, bl, wts, norm, lane, acc);
-      if (lane == 0) {
-        const long long il = (long long)yl * sp + xl2;
-#pragma unroll
-        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
-      }
-    }
+    const unsigned long long mask = __ballot(valid && bad);
+    if (mask)
+      recompute_flagged<N, TS>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm, mom,
+                               plane, sp, lane);
   }
 }
 
@@ -571,18 +617,40 @@ int gauss_tile_tx(int R, int N) {
   return tx >= 4 ? tx : 0;
 }
 
-StripGeom make_geom(int H, int W, int R, int target_waves) {
+// Segment height: the running sums pay a 2R-row warm-up per segment, so
+// segments should be long; but the grid should also fill the device in
+// whole rounds (a last, partly filled round of waves idles most CUs). The
+// height is the smallest that makes all waves fit in `capacity` resident
+// waves (one round), else two rounds, ..., capped at 64 rows.
+StripGeom make_geom(int H, int W, int R, long long capacity) {
   StripGeom g;
   g.Rpad = (R + kV - 1) / kV * kV;
   g.O = (kStrip - R - g.Rpad) / kV * kV;
   g.n_strips = (W + g.O - 1) / g.O;
-  // rows per segment: long segments amortise the 2R-row warm-up of the
-  // running sums; short ones give enough waves to fill the device
   int th = 64;
-  while (th > 8 && (long long)g.n_strips * ((H + th - 1) / th) < target_waves) th >>= 1;
+  for (long long m = 1; m <= 64; ++m) {
+    const long long segs = m * capacity / g.n_strips;
+    if (segs < 1) continue;
+    const long long t = (H + segs - 1) / segs;
+    if (t <= 64) {
+      th = (int)(t < 2 ? 2 : t);
+      break;
+    }
+  }
   g.TH = th;
   g.n_segs = (H + th - 1) / th;
   return g;
+}
+
+int device_cus() {
+  static int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+    return n;
+  }();
+  return cus;
 }
 
 template <int N, typename TS>
@@ -590,7 +658,17 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
                             double sigma_s, int R, const float* alpha, const float* beta,
                             long long sp, TS* mom, long long plane, hipStream_t stream,
                             const Batch& b) {
-  const StripGeom g = make_geom(h, w, R, 2560 / (b.n > 0 ? b.n : 1) + 1);
+  // resident waves of the box kernel on this device (occupancy x CUs); the
+  // segment geometry depends on the image and device only (not on the batch
+  // size), so an image gets bit-identical moments alone or in a batch
+  static const long long capacity = [] {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, moments_box<N, TS>, kWaves * kWave, 0) !=
+            hipSuccess || blocks < 1)
+      blocks = 2;
+    return (long long)blocks * kWaves * device_cus();
+  }();
+  const StripGeom g = make_geom(h, w, R, capacity);
   // largest tolerated shift amplification: FP64 stack keeps ~1e-8 relative
   // headroom; the FP32 stack only needs to stay below its own rounding
   const double cond_max = sizeof(TS) == 8 ? 1e8 : 1e12;
