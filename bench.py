@@ -5,9 +5,11 @@ A step is one pass of the whole fast filter (window bounds, moment stack,
 range stage) over one synthetic image already resident in HBM, issued as
 the three C-ABI calls abf_minmax -> abf_stack_moments -> abf_range on one
 stream (exactly what abf_fast does), with HIP events between them so each
-kernel group is timed live. The mixed-precision path is the headline
-value; the all-FP64 path and the GPU brute force are timed beside it, and
-parity against the CPU oracle is checked on sampled pixels.
+kernel is timed live. The mixed-precision path is the headline value; the
+all-FP64 path, the fused variant (abf_minmax -> abf_moments_range, moments
+and range stage in one kernel, no moment planes in HBM) and the GPU brute
+force are timed beside it, and parity against the CPU oracle is checked on
+sampled pixels.
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -52,6 +54,9 @@ def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
         "minmax": dict(bytes=px * (4 + 8), flops=0),
         "moments": dict(bytes=px * (4 + 8 + N * b), flops=px * (conv_flops + shift_flops)),
         "range": dict(bytes=px * (8 + N * b + tb + 4 + b), flops=px * range_flops),
+        # fused: f, alpha, beta, theta, sigma in; g^ out (the stack never leaves the CU)
+        "moments_range": dict(bytes=px * (4 + 8 + tb + 4 + b),
+                              flops=px * (conv_flops + shift_flops + range_flops)),
     }
 
 
@@ -102,9 +107,10 @@ def main():
     fd, td, sd = dev(f), dev(th), dev(sg)
     scratch = torch.empty(abf.lib().abf_scratch_bytes(H, W, R), dtype=torch.uint8, device="cuda")
 
-    def make_path(prec):
+    def make_path(prec, fused):
         stack = torch.empty(abf.stack_bytes(H, W, N, prec), dtype=torch.uint8, device="cuda")
         out = torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64, device="cuda")
+        names = ["minmax", "moments_range"] if fused else ["minmax", "moments", "range"]
 
         def step(ev=None):
             if ev is not None:
@@ -112,18 +118,23 @@ def main():
             abf.minmax_into_stack(fd, stack, R, N, prec, workspace=scratch)
             if ev is not None:
                 ev[1].record()
-            abf.stack_moments(fd, stack, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec)
+            if fused:
+                abf.moments_range(fd, stack, sd, theta=td, kernel=kernel, rho=R, N=N, sigma_s=ss,
+                                  precision=prec, out=out)
+            else:
+                abf.stack_moments(fd, stack, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec)
+                if ev is not None:
+                    ev[2].record()
+                abf.range_from_stack(stack, sd, img=fd, theta=td, N=N, precision=prec, out=out)
             if ev is not None:
-                ev[2].record()
-            abf.range_from_stack(stack, sd, img=fd, theta=td, N=N, precision=prec, out=out)
-            if ev is not None:
-                ev[3].record()
+                ev[len(names)].record()
 
-        return out, step
+        return out, step, names
 
-    def time_path(prec, steps, warmup):
-        out, step = make_path(prec)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    def time_path(prec, steps, warmup, fused=False):
+        out, step, names = make_path(prec, fused)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+               for _ in range(steps)]
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -133,10 +144,8 @@ def main():
             step(evs[i])
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / steps
-        stage_ms = {"minmax": [e[0].elapsed_time(e[1]) for e in evs],
-                    "moments": [e[1].elapsed_time(e[2]) for e in evs],
-                    "range": [e[2].elapsed_time(e[3]) for e in evs]}
-        total_ms = [e[0].elapsed_time(e[3]) for e in evs]
+        stage_ms = {nm: [e[j].elapsed_time(e[j + 1]) for e in evs] for j, nm in enumerate(names)}
+        total_ms = [e[0].elapsed_time(e[-1]) for e in evs]
         return out, stage_ms, total_ms, wall
 
     # ---------------------------------------------------------- timed region
@@ -144,6 +153,11 @@ def main():
     out_m, st_m, tot_m, wall_m = time_path("mixed", args.steps, args.warmup)
     log("timing fp64 path ...")
     out_d, st_d, tot_d, wall_d = time_path("fp64", args.steps, args.warmup)
+    log("timing the fused variant ...")
+    fu_steps = max(5, args.steps // 5)
+    out_s, st_s, tot_s, wall_s = time_path("mixed", fu_steps, 2, fused=True)
+    out_sd, st_sd, tot_sd, wall_sd = time_path("fp64", fu_steps, 2, fused=True)
+    fused_equal = bool(torch.equal(out_s, out_m) and torch.equal(out_sd, out_d))
 
     med = lambda v: float(np.median(v))
     # whole-job rate: K steps over the synchronised wall clock of the timed region
@@ -248,6 +262,10 @@ def main():
         "parity_pixels": int(len(ys)),
         "brute_force_fp64": {"value": round(mpix / (brute_ms * 1e-3), 3), "ms": round(brute_ms, 3)},
         "device_ms_per_step_median": {"mixed": round(med(tot_m), 5), "fp64": round(med(tot_d), 5)},
+        "fused_variant": {"mixed_ms_per_step": round(wall_s, 5), "fp64_ms_per_step": round(wall_sd, 5),
+                          "stage_ms_mixed": {k: round(med(v), 5) for k, v in st_s.items()},
+                          "stage_ms_fp64": {k: round(med(v), 5) for k, v in st_sd.items()},
+                          "output_equals_stack_path": fused_equal},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -60,6 +60,9 @@ enum { ABF_PREC_FP64 = 0, ABF_PREC_MIXED = 1 };
 /* ABF_FLAG_CLAMP: clip the output to [alpha_i, beta_i] (the fitted
  * polynomial may go negative, Sec. II-B); recommended, used by tests.     */
 enum { ABF_FLAG_CLAMP = 1u };
+/* ABF_FLAG_KEEP_STACK (abf_moments_range only): also store the moment
+ * planes in the stack, so that abf_range can reuse them later.            */
+enum { ABF_FLAG_KEEP_STACK = 2u };
 enum { ABF_N_MAX = 8, ABF_RHO_MAX = 96 };
 
 /* Human-readable name of a status code (static string). */
@@ -143,6 +146,25 @@ abf_status abf_range(const void* stack, size_t stack_bytes, const float* img,
                      const float* theta, const float* sigma, int h, int w,
                      long long pitch, int N, int precision, unsigned flags,
                      void* out, long long out_pitch, void* stream);
+
+/*
+ * abf_moments_range -- Algorithm 1 lines 6-20 in one pass per pixel: given
+ * a stack whose planes 0 and 1 hold alpha_i and beta_i (abf_minmax with
+ * out_pitch = abf_stack_pitch(w)), forms each pixel's moments (Props. 2-3)
+ * and finishes the filter from them in registers (the fit of eq. inv, the
+ * integrals, eq. BFfinal), without writing the moment planes unless flags
+ * has ABF_FLAG_KEEP_STACK. The output equals abf_stack_moments followed by
+ * abf_range, bit for bit. Arguments as for those two calls (theta and
+ * sigma share `pitch` with img; theta NULL means theta = img).
+ * It moves fewer bytes than the stack path but holds the range stage's
+ * registers through the moment pass, which lowers occupancy; on MI355X it
+ * is the slower of the two, so abf_fast uses the stack path.
+ */
+abf_status abf_moments_range(const float* img, const float* theta, const float* sigma,
+                             int h, int w, long long pitch, int kernel_kind,
+                             double sigma_s, int rho, int N, int precision,
+                             unsigned flags, void* stack, size_t stack_bytes,
+                             void* out, long long out_pitch, void* stream);
 
 /*
  * abf_fast -- the whole fast filter (Algorithm 1) on one image:

@@ -19,13 +19,14 @@ import os
 __all__ = [
     "lib", "library_path", "fast", "bruteforce", "minmax", "moment_stack",
     "range_from_stack", "fast_batched", "minmax_into_stack", "stack_moments",
-    "fast_strided", "sigma_local_std", "workspace_bytes", "stack_bytes",
+    "fast_strided", "sigma_local_std", "moments_range", "workspace_bytes", "stack_bytes",
     "stack_planes", "Request", "KERNELS", "PRECISIONS", "ABFError",
 ]
 
 KERNELS = {"box": 0, "gaussian": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FLAG_CLAMP = 1
+FLAG_KEEP_STACK = 2
 N_MAX = 8
 RHO_MAX = 96
 
@@ -74,6 +75,7 @@ def lib():
         "abf_moment_stack": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp, sz, vp], i),
         "abf_stack_moments": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp], i),
         "abf_range": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
+        "abf_moments_range": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, sz, vp, ll, vp], i),
         "abf_fast": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, ll, vp, sz, vp], i),
         "abf_bruteforce": ([vp, vp, vp, i, i, ll, i, d, i, i, vp, ll, vp], i),
         "abf_batched_workspace_bytes": ([ctypes.POINTER(Request), i, i], sz),
@@ -288,6 +290,26 @@ def range_from_stack(stack, sigma, img=None, theta=None, N=5, precision="mixed",
                          pitch, int(N), p, FLAG_CLAMP if clamp else 0, _ptr(out), out.stride(0),
                          _stream(stream))
     _check(st, "abf_range")
+    return out
+
+
+def moments_range(img, stack, sigma, theta=None, kernel="box", rho=3, N=5, sigma_s=0.0,
+                  precision="mixed", clamp=True, keep_stack=False, out=None, stream=None):
+    """abf_moments_range: moments and range stage in one pass from a stack
+    whose bound planes are present (``minmax_into_stack``); with
+    ``keep_stack`` the moment planes are stored too."""
+    torch = _torch()
+    img, sigma, theta = _plane(img, "img"), _plane(sigma, "sigma"), _plane(theta, "theta")
+    h, w = img.shape
+    pitch = _common_pitch(img, sigma, theta)
+    p = _prec(precision)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+    flags = (FLAG_CLAMP if clamp else 0) | (FLAG_KEEP_STACK if keep_stack else 0)
+    st = lib().abf_moments_range(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
+                                 float(sigma_s), int(rho), int(N), p, flags, _ptr(stack),
+                                 stack.numel(), _ptr(out), out.stride(0), _stream(stream))
+    _check(st, "abf_moments_range")
     return out
 
 

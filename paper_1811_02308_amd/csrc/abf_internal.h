@@ -81,13 +81,30 @@ hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rh
                          float* alpha, float* beta, long long out_pitch,
                          void* scratch, hipStream_t stream, const Batch& b = Batch());
 
+// Range-stage operands for a moments launch that also finishes the filter
+// (theta and sigma share tpitch; out has the stack's element type). With
+// keep_stack = 0 the moment planes are not written.
+struct FuseSpec {
+  const float* theta = nullptr;
+  const float* sigma = nullptr;
+  long long tpitch = 0;
+  void* out = nullptr;
+  long long opitch = 0;
+  unsigned flags = 0;
+  int keep_stack = 0;
+};
+
 // prec: 0 = FP64 stack, 1 = FP32 stack. N >= 1. The alpha/beta planes of the
-// stack must already hold the window bounds.
+// stack must already hold the window bounds. fuse != nullptr also evaluates
+// the range stage per pixel and writes the filtered output (only where
+// moments_fusable() holds); the result equals launch_range() on the stack.
 hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           int kernel_kind, double sigma_s, int rho, int N, int prec,
                           const float* alpha, const float* beta, long long sp,
                           void* mom, long long plane_elems, hipStream_t stream,
-                          const Batch& b = Batch());
+                          const Batch& b = Batch(), const FuseSpec* fuse = nullptr);
+
+bool moments_fusable(int kernel_kind, int rho, int N);
 
 hipError_t launch_range(const float* alpha, const float* beta, long long sp,
                         const void* mom, long long plane_elems,

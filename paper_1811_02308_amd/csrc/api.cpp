@@ -185,12 +185,64 @@ abf_status abf_range(const void* stack, size_t stack_bytes, const float* img, co
                                       flags, out, out_pitch, static_cast<hipStream_t>(stream)));
 }
 
+// Moments and range stage of one image or a strided batch, alpha/beta
+// already in the stack(s). fused: one kernel where the moment kernel
+// supports it; otherwise (or fused = false) the stack path: the moment
+// kernel writes the stack, then the range kernel reads it.
+static abf_status moments_range_batch(const float* img, const float* theta, const float* sigma,
+                                      int h, int w, long long pitch, int kernel_kind,
+                                      double sigma_s, int rho, int N, int precision,
+                                      unsigned flags, char* stack, void* out, long long out_pitch,
+                                      hipStream_t s, const abf::Batch& b, bool fused) {
+  const long long sp = abf_stack_pitch(w);
+  const float* alpha = reinterpret_cast<const float*>(stack);
+  const float* beta =
+      reinterpret_cast<const float*>(stack + abf_stack_plane_offset(h, w, N, precision, 1));
+  void* mom = stack + abf_stack_plane_offset(h, w, N, precision, 2);
+  const int pc = precision == ABF_PREC_FP64 ? 0 : 1;
+  const float* th = theta ? theta : img;
+  const unsigned rflags = flags & ABF_FLAG_CLAMP;
+  if (fused && N > 0 && abf::moments_fusable(kernel_kind, rho, N)) {
+    abf::FuseSpec fs;
+    fs.theta = th;
+    fs.sigma = sigma;
+    fs.tpitch = pitch;
+    fs.out = out;
+    fs.opitch = out_pitch;
+    fs.flags = rflags;
+    fs.keep_stack = (flags & ABF_FLAG_KEEP_STACK) ? 1 : 0;
+    return hip_status(abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, pc,
+                                          alpha, beta, sp, mom, sp * h, s, b, &fs));
+  }
+  if (N > 0) {
+    const hipError_t e = abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, pc,
+                                             alpha, beta, sp, mom, sp * h, s, b);
+    if (e != hipSuccess) return ABF_E_HIP;
+  }
+  return hip_status(abf::launch_range(alpha, beta, sp, mom, sp * h, th, pitch, sigma, pitch, h, w,
+                                      N, pc, rflags, out, out_pitch, s, b));
+}
+
+abf_status abf_moments_range(const float* img, const float* theta, const float* sigma, int h,
+                             int w, long long pitch, int kernel_kind, double sigma_s, int rho,
+                             int N, int precision, unsigned flags, void* stack,
+                             size_t stack_bytes, void* out, long long out_pitch, void* stream) {
+  if (!img || !sigma || !out || !stack || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0 ||
+      N < 0 || !prec_ok(precision) || !kind_ok(kernel_kind) || !std::isfinite(sigma_s))
+    return ABF_E_INVALID;
+  if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (!aligned(stack) || stack_bytes < abf_stack_bytes(h, w, N, precision)) return ABF_E_WORKSPACE;
+  return moments_range_batch(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N,
+                             precision, flags, static_cast<char*>(stack), out, out_pitch,
+                             static_cast<hipStream_t>(stream), abf::Batch(), true);
+}
+
 abf_status abf_fast(const float* img, const float* theta, const float* sigma, int h, int w,
                     long long pitch, int kernel_kind, double sigma_s, int rho, int N,
                     int precision, unsigned flags, void* out, long long out_pitch,
                     void* workspace, size_t workspace_bytes, void* stream) {
   if (!img || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0 || N < 0 ||
-      !prec_ok(precision) || !kind_ok(kernel_kind))
+      !prec_ok(precision) || !kind_ok(kernel_kind) || !std::isfinite(sigma_s))
     return ABF_E_INVALID;
   if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
   if (!workspace || !aligned(workspace) ||
@@ -198,11 +250,14 @@ abf_status abf_fast(const float* img, const float* theta, const float* sigma, in
     return ABF_E_WORKSPACE;
   const size_t sb = abf_stack_bytes(h, w, N, precision);
   char* ws = static_cast<char*>(workspace);
-  abf_status st = abf_moment_stack(img, h, w, pitch, kernel_kind, sigma_s, rho, N, precision, ws,
-                                   sb, ws + sb, workspace_bytes - sb, stream);
-  if (st != ABF_OK) return st;
-  return abf_range(ws, sb, img, theta, sigma, h, w, pitch, N, precision, flags, out, out_pitch,
-                   stream);
+  const long long sp = abf_stack_pitch(w);
+  float* alpha = reinterpret_cast<float*>(ws);
+  float* beta = reinterpret_cast<float*>(ws + abf_stack_plane_offset(h, w, N, precision, 1));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, ws + sb, s);
+  if (e != hipSuccess) return ABF_E_HIP;
+  return moments_range_batch(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N,
+                             precision, flags, ws, out, out_pitch, s, abf::Batch(), false);
 }
 
 abf_status abf_bruteforce(const float* img, const float* theta, const float* sigma, int h, int w,
@@ -283,17 +338,10 @@ abf_status abf_fast_strided(const float* img, const float* theta, const float* s
   b.out = n > 1 ? out_image_stride : 0;
   float* alpha = reinterpret_cast<float*>(base);
   float* beta = reinterpret_cast<float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
-  void* mom = base + abf_stack_plane_offset(h, w, N, precision, 2);
-  const int pc = precision == ABF_PREC_FP64 ? 0 : 1;
-  hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, scratch, s, b);
+  const hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, scratch, s, b);
   if (e != hipSuccess) return ABF_E_HIP;
-  if (N > 0) {
-    e = abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, pc, alpha, beta, sp,
-                            mom, sp * h, s, b);
-    if (e != hipSuccess) return ABF_E_HIP;
-  }
-  return hip_status(abf::launch_range(alpha, beta, sp, mom, sp * h, theta ? theta : img, pitch,
-                                      sigma, pitch, h, w, N, pc, flags, out, out_pitch, s, b));
+  return moments_range_batch(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N,
+                             precision, flags, base, out, out_pitch, s, b, false);
 }
 
 abf_status abf_sigma_local_std(const float* img, int n, int h, int w, long long pitch,

@@ -31,6 +31,7 @@
 // (O(R) per pixel); for radii too large for its LDS tile, the strip layout
 // of the box kernel with direct weighted sums.
 #include "abf_internal.h"
+#include "range_eval.h"
 
 namespace abf {
 namespace {
@@ -127,6 +128,49 @@ __device__ __forceinline__ bool legendre_from_moments(double (&m)[N + 1], float 
   return false;
 }
 
+// Fused range stage: theta (or f), sigma, the output and the quadrature rule
+// for kernels that finish each pixel's filter right after its moments
+// (the range half of Algorithm 1 in registers). keep_stack also stores the
+// moments in the stack.
+struct FuseArgs {
+  const float* theta;
+  const float* sigma;
+  long long tpitch;
+  void* out;
+  long long opitch;
+  unsigned flags;
+  int keep_stack;
+  GLArgs gl;
+};
+
+// Completes pixel (y, x) from its Legendre moments m[1..N]: stores them
+// (stack path, or fused with keep_stack) and, when fused, evaluates the
+// range stage and writes the output. The moments enter the range stage
+// rounded to the stack's type, so the fused result equals the stack path's.
+template <int N, typename TS, bool FUSED>
+__device__ __forceinline__ void finish_pixel(const double (&m)[N + 1], float a, float b, int y,
+                                             int x, long long idx, TS* __restrict__ mom,
+                                             long long plane, const FuseArgs& fz) {
+  if (!FUSED || fz.keep_stack) {
+#pragma unroll
+    for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
+  }
+  if (FUSED) {
+    TS* o = static_cast<TS*>(fz.out) + (long long)y * fz.opitch + x;
+    if (a == b) {
+      *o = TS(a);
+    } else {
+      double ak[N + 1];
+      ak[0] = 1.0;
+#pragma unroll
+      for (int k = 1; k <= N; ++k) ak[k] = (2.0 * k + 1.0) * (double)TS(m[k]);
+      const long long ti = (long long)y * fz.tpitch + x;
+      *o = TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)fz.theta[ti], (double)fz.sigma[ti],
+                                              fz.flags, fz.gl));
+    }
+  }
+}
+
 // Direct evaluation of a~_k = sum_j omega_j P_k(z_j) for one pixel (y, x),
 // z_j = (f(i-j) - mid) / half, by the whole wave: lanes split the window's
 // taps, each evaluates P_1..P_N by the three-term recurrence, and the
@@ -201,20 +245,18 @@ __device__ __forceinline__ void direct_legendre_lane(const float* __restrict__ i
 
 // Recompute the flagged pixels of a wave: one pixel at a time by the whole
 // wave when few are flagged, every flagged lane its own pixel when many are.
-template <int N, typename TS>
+template <int N, typename TS, bool FUSED>
 __device__ __forceinline__ void recompute_flagged(unsigned long long mask, bool mine, int y, int x,
                                                   float a, float b, const float* __restrict__ img,
                                                   long long pitch, int H, int W, int R,
                                                   const double* __restrict__ wts, double norm,
                                                   TS* __restrict__ mom, long long plane,
-                                                  long long sp, int lane) {
+                                                  long long sp, int lane, const FuseArgs& fz) {
   if (__popcll(mask) > 24) {
     if (mine) {
       double acc[N + 1];
       direct_legendre_lane<N>(img, pitch, H, W, R, y, x, a, b, wts, norm, acc);
-      const long long il = (long long)y * sp + x;
-#pragma unroll
-      for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
+      finish_pixel<N, TS, FUSED>(acc, a, b, y, x, (long long)y * sp + x, mom, plane, fz);
     }
     return;
   }
@@ -225,11 +267,8 @@ __device__ __forceinline__ void recompute_flagged(unsigned long long mask, bool 
     const float al = __shfl(a, l, kWave), bl = __shfl(b, l, kWave);
     double acc[N + 1];
     direct_legendre<N>(img, pitch, H, W, R, yl, xl, al, bl, wts, norm, lane, acc);
-    if (lane == 0) {
-      const long long il = (long long)yl * sp + xl;
-#pragma unroll
-      for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + il] = TS(acc[k]);
-    }
+    if (lane == 0)
+      finish_pixel<N, TS, FUSED>(acc, al, bl, yl, xl, (long long)yl * sp + xl, mom, plane, fz);
   }
 }
 
@@ -237,14 +276,15 @@ __device__ __forceinline__ void recompute_flagged(unsigned long long mask, bool 
 // columns j0 + lane; `sum_k(j, k)` returns the normalised window moment of
 // u^(k+1) for strip column j. Ill-conditioned pixels are recomputed by the
 // whole wave with direct_legendre.
-template <int N, typename TS, typename SumFn>
+template <int N, typename TS, bool FUSED, typename SumFn>
 __device__ __forceinline__ void epilogue_row(SumFn sum_k, int y, int xo, int O, int W, int H,
                                              int R, const float* __restrict__ img, long long pitch,
                                              const float* __restrict__ alpha,
                                              const float* __restrict__ beta, long long sp,
                                              double c, double cond_max,
                                              const double* __restrict__ wts, double norm,
-                                             TS* __restrict__ mom, long long plane, int lane) {
+                                             TS* __restrict__ mom, long long plane, int lane,
+                                             const FuseArgs& fz) {
   for (int j0 = 0; j0 < O; j0 += kWave) {
     const int j = j0 + lane;
     const bool valid = j < O && xo + j < W;
@@ -260,15 +300,12 @@ __device__ __forceinline__ void epilogue_row(SumFn sum_k, int y, int xo, int O, 
       a = alpha[idx];
       b = beta[idx];
       bad = legendre_from_moments<N>(m, a, b, c, cond_max);
-      if (!bad) {
-#pragma unroll
-        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
-      }
+      if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
     }
     const unsigned long long mask = __ballot(valid && bad);
     if (mask)
-      recompute_flagged<N, TS>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm, mom,
-                               plane, sp, lane);
+      recompute_flagged<N, TS, FUSED>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm,
+                                      mom, plane, sp, lane, fz);
   }
 }
 
@@ -298,13 +335,19 @@ struct StripGeom {
   int n_segs;
 };
 
-template <int N, typename TS>
+template <int N, typename TS, bool FUSED>
 __global__ __launch_bounds__(kWaves * kWave) void moments_box(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4, Batch bt) {
+    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4, Batch bt,
+    FuseArgs fz) {
   __shared__ double sh[kWaves][N][kStripPad];
   img += blockIdx.y * bt.img;
+  if (FUSED) {
+    fz.theta += blockIdx.y * bt.img;
+    fz.sigma += blockIdx.y * bt.img;
+    fz.out = static_cast<TS*>(fz.out) + blockIdx.y * bt.out;
+  }
   alpha = byte_offset(alpha, blockIdx.y * bt.stack);
   beta = byte_offset(beta, blockIdx.y * bt.stack);
   mom = byte_offset(mom, blockIdx.y * bt.stack);
@@ -401,8 +444,8 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
       const double lo = (e - R - 1 >= 0) ? sh[wv][k][pidx(e - R - 1)] : 0.0;
       return (hi - lo) * inv_area;
     };
-    epilogue_row<N, TS>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c, cond_max,
-                        nullptr, inv_area, mom, plane, lane);
+    epilogue_row<N, TS, FUSED>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c,
+                               cond_max, nullptr, inv_area, mom, plane, lane, fz);
     wave_sync();
   }
 }
@@ -470,31 +513,39 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
       for (int dx = -R; dx <= R; ++dx) acc = fma(wts[dx + R], sh[wv][k][e + dx], acc);
       return acc * iz;
     };
-    epilogue_row<N, TS>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c, cond_max,
-                        wts, iz * iz, mom, plane, lane);
+    epilogue_row<N, TS, false>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c,
+                               cond_max, wts, iz * iz, mom, plane, lane, FuseArgs{});
     wave_sync();
   }
 }
 
 // Gaussian kernel, tiled: a workgroup computes a kTY x TX tile of outputs.
+// (Tile sizes keep the LDS tile at 30-40 KiB so that four workgroups share a
+// CU.)
 // Phase 1 (vertical): thread t owns padded column t, reads its kTY + 2R
 // inputs once (coalesced across threads), forms the powers once per input
 // and accumulates the kTY x N vertical weighted sums in registers; the sums
-// go to LDS. Phase 2 (horizontal): a thread owns 4 adjacent output columns
-// of one row and accumulates their 4 x N horizontal weighted sums from the
-// (4 + 2R) LDS columns they span. Phase 3: shift and Legendre basis per
+// go to LDS. Phase 2 (horizontal): a thread owns kCB adjacent output columns
+// of one row and accumulates their kCB x N horizontal weighted sums from the
+// (kCB + 2R) LDS columns they span. Phase 3: shift and Legendre basis per
 // pixel (same epilogue as the box kernel, with the exact recompute for
 // ill-conditioned pixels). Work per pixel is O(R), as for the paper's
 // direct convolution.
-constexpr int kTY = 8;
+constexpr int kTY = 4;   // output rows per tile
+constexpr int kCB = 2;   // adjacent output columns per thread in the horizontal phase
 
-template <int N, typename TS>
+template <int N, typename TS, bool FUSED>
 __global__ __launch_bounds__(256) void moments_gauss_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R, int TX, double inv2s2,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, double cond_max, Batch bt) {
+    TS* __restrict__ mom, long long plane, double cond_max, Batch bt, FuseArgs fz) {
   extern __shared__ double vsum[];            // [N][kTY][E]
   img += blockIdx.z * bt.img;
+  if (FUSED) {
+    fz.theta += blockIdx.z * bt.img;
+    fz.sigma += blockIdx.z * bt.img;
+    fz.out = static_cast<TS*>(fz.out) + blockIdx.z * bt.out;
+  }
   alpha = byte_offset(alpha, blockIdx.z * bt.stack);
   beta = byte_offset(beta, blockIdx.z * bt.stack);
   mom = byte_offset(mom, blockIdx.z * bt.stack);
@@ -551,23 +602,23 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   }
   __syncthreads();
 
-  // phase 2: horizontal sums for 4 adjacent outputs of one row
-  const int groups = TX / 4;
+  // phase 2: horizontal sums for kCB adjacent outputs of one row
+  const int groups = TX / kCB;
   const int r = t / groups, gq = t - r * groups;
   const bool active = r < kTY;
-  const int xl = 4 * gq;
-  double m4[4][N + 1];
+  const int xl = kCB * gq;
+  double m4[kCB][N + 1];
   if (active) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < kCB; ++v)
 #pragma unroll
       for (int k = 0; k <= N; ++k) m4[v][k] = 0.0;
-    for (int j = 0; j < 4 + 2 * R; ++j) {
+    for (int j = 0; j < kCB + 2 * R; ++j) {
       double val[N];
 #pragma unroll
       for (int k = 0; k < N; ++k) val[k] = vsum[(k * kTY + r) * E + xl + j];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
+      for (int v = 0; v < kCB; ++v) {
         const int d = j - v;
         if (d >= 0 && d <= 2 * R) {
           const double wv = wts[d];
@@ -580,7 +631,7 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   // phase 3: per-pixel epilogue (all lanes take part in the wave ballots)
   const double norm = iz * iz;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
+  for (int v = 0; v < kCB; ++v) {
     const int y = y0 + r, x = x0 + xl + v;
     const bool valid = active && y < H && x < W && xl + v < TX;
     const long long idx = (long long)(valid ? y : 0) * sp + (valid ? x : 0);
@@ -594,27 +645,24 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
       a = alpha[idx];
       b = beta[idx];
       bad = legendre_from_moments<N>(m, a, b, c, cond_max);
-      if (!bad) {
-#pragma unroll
-        for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
-      }
+      if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
     }
     const unsigned long long mask = __ballot(valid && bad);
     if (mask)
-      recompute_flagged<N, TS>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm, mom,
-                               plane, sp, lane);
+      recompute_flagged<N, TS, FUSED>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm,
+                                      mom, plane, sp, lane, fz);
   }
 }
 
 // Output columns per Gaussian tile: at most 128, with the LDS tile
 // kTY x (TX + 2R) x N doubles within 64 KiB; 0 if R is too large.
 int gauss_tile_tx(int R, int N) {
-  int e = 1024 / N;
-  if (e > 256) e = 256;
+  int e = 65536 / (kTY * 8 * N);          // padded columns within 64 KiB of LDS
+  if (e > 256) e = 256;                   // one phase-1 thread per padded column
   int tx = e - 2 * R;
-  if (tx > 128) tx = 128;
-  tx &= ~3;
-  return tx >= 4 ? tx : 0;
+  if (tx > 128) tx = 128;                 // kTY * tx / kCB <= 256 phase-2 threads
+  tx &= ~(kCB - 1);
+  return tx >= kCB ? tx : 0;
 }
 
 // Segment height: the running sums pay a 2R-row warm-up per segment, so
@@ -657,13 +705,14 @@ template <int N, typename TS>
 hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int kind,
                             double sigma_s, int R, const float* alpha, const float* beta,
                             long long sp, TS* mom, long long plane, hipStream_t stream,
-                            const Batch& b) {
+                            const Batch& b, const FuseSpec* fs) {
   // resident waves of the box kernel on this device (occupancy x CUs); the
   // segment geometry depends on the image and device only (not on the batch
   // size), so an image gets bit-identical moments alone or in a batch
   static const long long capacity = [] {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, moments_box<N, TS>, kWaves * kWave, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, moments_box<N, TS, false>,
+                                                     kWaves * kWave, 0) !=
             hipSuccess || blocks < 1)
       blocks = 2;
     return (long long)blocks * kWaves * device_cus();
@@ -673,12 +722,27 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   // headroom; the FP32 stack only needs to stay below its own rounding
   const double cond_max = sizeof(TS) == 8 ? 1e8 : 1e12;
   const int waves = g.n_strips * g.n_segs;
+  FuseArgs fz{};
+  if (fs) {
+    fz.theta = fs->theta;
+    fz.sigma = fs->sigma;
+    fz.tpitch = fs->tpitch;
+    fz.out = fs->out;
+    fz.opitch = fs->opitch;
+    fz.flags = fs->flags;
+    fz.keep_stack = fs->keep_stack;
+    fz.gl = make_gl_args(sizeof(TS) == 4);
+  }
   if (kind == 0) {
     dim3 grid((waves + kWaves - 1) / kWaves, b.n);
     const int vec4 = (pitch % 4 == 0) && (b.img % 4 == 0) &&
                      (reinterpret_cast<uintptr_t>(img) % 16 == 0);
-    hipLaunchKernelGGL((moments_box<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
-                       img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b);
+    if (fs)
+      hipLaunchKernelGGL((moments_box<N, TS, true>), grid, dim3(kWaves * kWave), 0, stream, img,
+                         pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b, fz);
+    else
+      hipLaunchKernelGGL((moments_box<N, TS, false>), grid, dim3(kWaves * kWave), 0, stream, img,
+                         pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b, fz);
     return hipGetLastError();
   }
   const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
@@ -686,10 +750,16 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   if (tx > 0) {
     dim3 tg((w + tx - 1) / tx, (h + kTY - 1) / kTY, b.n);
     const size_t lds = (size_t)N * kTY * (tx + 2 * R) * sizeof(double);
-    hipLaunchKernelGGL((moments_gauss_tile<N, TS>), tg, dim3(256), lds, stream, img, pitch, h,
-                       w, R, tx, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, cond_max, b);
+    const double i2 = 1.0 / (2.0 * s * s);
+    if (fs)
+      hipLaunchKernelGGL((moments_gauss_tile<N, TS, true>), tg, dim3(256), lds, stream, img,
+                         pitch, h, w, R, tx, i2, alpha, beta, sp, mom, plane, cond_max, b, fz);
+    else
+      hipLaunchKernelGGL((moments_gauss_tile<N, TS, false>), tg, dim3(256), lds, stream, img,
+                         pitch, h, w, R, tx, i2, alpha, beta, sp, mom, plane, cond_max, b, fz);
     return hipGetLastError();
   }
+  if (fs) return hipErrorNotSupported;   // callers check moments_fusable() first
   dim3 grid((waves + kWaves - 1) / kWaves);
   for (int z = 0; z < b.n; ++z)
     hipLaunchKernelGGL((moments_gauss<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
@@ -703,10 +773,10 @@ template <typename TS>
 hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, int kind,
                       double sigma_s, int R, const float* alpha, const float* beta,
                       long long sp, TS* mom, long long plane, hipStream_t stream,
-                      const Batch& b) {
+                      const Batch& b, const FuseSpec* fs) {
   switch (N) {
 #define ABF_CASE(n) \
-  case n: return launch_moments_t<n, TS>(img, pitch, h, w, kind, sigma_s, R, alpha, beta, sp, mom, plane, stream, b);
+  case n: return launch_moments_t<n, TS>(img, pitch, h, w, kind, sigma_s, R, alpha, beta, sp, mom, plane, stream, b, fs);
     ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6) ABF_CASE(7) ABF_CASE(8)
 #undef ABF_CASE
     default: return hipErrorInvalidValue;
@@ -718,12 +788,17 @@ hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, in
 hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           int kernel_kind, double sigma_s, int rho, int N, int prec,
                           const float* alpha, const float* beta, long long sp,
-                          void* mom, long long plane_elems, hipStream_t stream, const Batch& b) {
+                          void* mom, long long plane_elems, hipStream_t stream, const Batch& b,
+                          const FuseSpec* fuse) {
   if (prec == 0)
     return dispatch_n<double>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
-                              static_cast<double*>(mom), plane_elems, stream, b);
+                              static_cast<double*>(mom), plane_elems, stream, b, fuse);
   return dispatch_n<float>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
-                           static_cast<float*>(mom), plane_elems, stream, b);
+                           static_cast<float*>(mom), plane_elems, stream, b, fuse);
+}
+
+bool moments_fusable(int kernel_kind, int rho, int N) {
+  return N >= 1 && (kernel_kind == 0 || gauss_tile_tx(rho, N) > 0);
 }
 
 }  // namespace abf

@@ -257,3 +257,41 @@ def test_stack_reuse_for_new_theta_sigma(torch, abf):
         a = abf.range_from_stack(st, dev(torch, sg), img=dev(torch, f), theta=dev(torch, th), N=6)
         b = abf.fast(dev(torch, f), dev(torch, sg), theta=dev(torch, th), rho=4, N=6)
         assert torch.equal(a, b)
+
+
+FUSED_CASES = [("box", 3, 5), ("box", 20, 8), ("box", 5, 1), ("gaussian", 15, 6), ("gaussian", 4, 8),
+               ("gaussian", 40, 7)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kernel,R,N", FUSED_CASES)
+def test_fused_equals_stack_path(torch, abf, precision, kernel, R, N):
+    """abf_moments_range (moments and range stage in one kernel) against the
+    stack path (abf_moment_stack + abf_range, as in abf_fast): bit-identical,
+    with and without keeping the stack. The image mixes noisy rectangles with
+    near-flat bright patches, whose windows take the exact recompute for
+    ill-conditioned shifts."""
+    f = rect_scene(60 + R, 150, 700, n_rect=10, noise=0.7, side_lo=10, side_hi=90)
+    f[40:90, 100:400] = np.float32(250.0) + (np.arange(300, dtype=np.float32) % 3) * np.float32(0.25)
+    sg = smooth_field(np.random.default_rng(R + N), *f.shape, 4, 60)
+    th = (f + smooth_field(np.random.default_rng(R), *f.shape, -15, 15)).astype(np.float32)
+    img, sgd, thd = dev(torch, f), dev(torch, sg), dev(torch, th)
+    st = abf.moment_stack(img, kernel=kernel, rho=R, N=N, precision=precision)
+    ref = abf.range_from_stack(st, sgd, img=img, theta=thd, N=N, precision=precision)
+    out = abf.fast(img, sgd, theta=thd, kernel=kernel, rho=R, N=N, precision=precision)
+    st1 = torch.zeros_like(st)
+    abf.minmax_into_stack(img, st1, R, N, precision=precision)
+    out1 = abf.moments_range(img, st1, sgd, theta=thd, kernel=kernel, rho=R, N=N,
+                             precision=precision)
+    # keep_stack: the fused kernel's stored moments equal the stack path's
+    st2 = torch.zeros_like(st)
+    abf.minmax_into_stack(img, st2, R, N, precision=precision)
+    out2 = abf.moments_range(img, st2, sgd, theta=thd, kernel=kernel, rho=R, N=N,
+                             precision=precision, keep_stack=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    assert torch.equal(out1, ref)
+    assert torch.equal(out2, ref)
+    for p, q in zip(abf.stack_planes(st, *f.shape, N, precision)[2],
+                    abf.stack_planes(st2, *f.shape, N, precision)[2]):
+        assert torch.equal(p, q)
