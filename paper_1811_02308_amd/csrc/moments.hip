@@ -39,12 +39,14 @@ namespace {
 constexpr int kV = 4;                    // columns per lane
 constexpr int kStrip = kWave * kV;       // padded columns per wave
 constexpr int kWaves = 4;                // waves per workgroup
-constexpr int kStripPad = kStrip + kStrip / 8;
-
-// LDS slot of padded column e: one pad double per 8, so that both the
-// 4-columns-per-lane writes and the consecutive-column reads of the
-// epilogue spread over the banks.
-__device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
+// LDS layout of a strip row in the box kernel: padded column e = 4 l + v
+// (lane l, its v-th column) sits at v * kSlotStride + l. The prefix writes
+// (fixed v, consecutive lanes) are contiguous, and the epilogue's reads of
+// consecutive columns step through the four v-rows, whose offset of 68
+// doubles puts 16 consecutive columns in 16 different bank pairs.
+constexpr int kSlotStride = kWave + 4;
+constexpr int kStripSlots = kV * kSlotStride;
+__device__ __forceinline__ int pidx(int e) { return (e & (kV - 1)) * kSlotStride + (e >> 2); }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -92,9 +94,10 @@ __device__ __forceinline__ bool legendre_from_moments(double (&m)[N + 1], float 
   }
   const double mid = 0.5 * ((double)a + (double)b) - c;
   const double half = 0.5 * ((double)b - (double)a);
+  const double ih = 1.0 / half;
   // The shift below amplifies the rounding of m_r by about
   // rho^k, rho = (|mid| + half) / half.
-  const double rho = (fabs(mid) + half) / half;
+  const double rho = fma(fabs(mid), ih, 1.0);
   double rn = rho;
 #pragma unroll
   for (int k = 1; k < N; ++k) rn *= rho;
@@ -107,7 +110,6 @@ __device__ __forceinline__ bool legendre_from_moments(double (&m)[N + 1], float 
 #pragma unroll
     for (int k = N; k > j; --k) m[k] = fma(s, m[k - 1], m[k]);
   // scale to z in [-1, 1]
-  const double ih = 1.0 / half;
   double sc = ih;
 #pragma unroll
   for (int k = 1; k <= N; ++k) {
@@ -272,20 +274,41 @@ __device__ __forceinline__ void recompute_flagged(unsigned long long mask, bool 
   }
 }
 
+// Window bounds of one output row of a strip, lane `lane` holding output
+// columns j0 + lane for the kChunks chunks j0 = 0, 64, ...: issued early so
+// the loads overlap the row's other work.
+constexpr int kChunks = kStrip / kWave;
+static_assert(kChunks == 4, "epilogue_row selects among four bound registers");
+__device__ __forceinline__ void load_bounds_row(const float* __restrict__ alpha,
+                                                const float* __restrict__ beta, long long sp,
+                                                int y, int xo, int O, int W, int lane,
+                                                float (&pa)[kChunks], float (&pb)[kChunks]) {
+#pragma unroll
+  for (int q = 0; q < kChunks; ++q) {
+    const int j = q * kWave + lane;
+    const int x = min(xo + min(j, O - 1), W - 1);
+    pa[q] = alpha[(long long)y * sp + x];
+    pb[q] = beta[(long long)y * sp + x];
+  }
+}
+
 // Epilogue for one output row of a wave: lanes take consecutive output
 // columns j0 + lane; `sum_k(j, k)` returns the normalised window moment of
-// u^(k+1) for strip column j. Ill-conditioned pixels are recomputed by the
-// whole wave with direct_legendre.
+// u^(k+1) for strip column j; pa/pb hold the row's bounds
+// (load_bounds_row). Ill-conditioned pixels are recomputed by the whole
+// wave with direct_legendre.
 template <int N, typename TS, bool FUSED, typename SumFn>
 __device__ __forceinline__ void epilogue_row(SumFn sum_k, int y, int xo, int O, int W, int H,
                                              int R, const float* __restrict__ img, long long pitch,
-                                             const float* __restrict__ alpha,
-                                             const float* __restrict__ beta, long long sp,
+                                             const float (&pa)[kChunks],
+                                             const float (&pb)[kChunks], long long sp,
                                              double c, double cond_max,
                                              const double* __restrict__ wts, double norm,
                                              TS* __restrict__ mom, long long plane, int lane,
                                              const FuseArgs& fz) {
-  for (int j0 = 0; j0 < O; j0 += kWave) {
+  for (int q = 0; q < kChunks; ++q) {
+    const int j0 = q * kWave;
+    if (j0 >= O) break;
     const int j = j0 + lane;
     const bool valid = j < O && xo + j < W;
     const int x = valid ? xo + j : xo;
@@ -297,8 +320,8 @@ __device__ __forceinline__ void epilogue_row(SumFn sum_k, int y, int xo, int O, 
       m[0] = 1.0;
 #pragma unroll
       for (int k = 0; k < N; ++k) m[k + 1] = sum_k(j, k);
-      a = alpha[idx];
-      b = beta[idx];
+      a = q == 0 ? pa[0] : q == 1 ? pa[1] : q == 2 ? pa[2] : pa[3];
+      b = q == 0 ? pb[0] : q == 1 ? pb[1] : q == 2 ? pb[2] : pb[3];
       bad = legendre_from_moments<N>(m, a, b, c, cond_max);
       if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
     }
@@ -341,7 +364,7 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
     TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4, Batch bt,
     FuseArgs fz) {
-  __shared__ double sh[kWaves][N][kStripPad];
+  __shared__ double sh[kWaves][N][kStripSlots];
   img += blockIdx.y * bt.img;
   if (FUSED) {
     fz.theta += blockIdx.y * bt.img;
@@ -402,17 +425,28 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
   }
 
   const double inv_area = 1.0 / ((double)(2 * R + 1) * (double)(2 * R + 1));
+  // the rows entering and leaving the window at y + 1, loaded one row ahead
+  float qi[kV], qo[kV];
+  auto load_step = [&](int yn) {
+    load4(img + (long long)min(yn + R, H - 1) * pitch, qi);
+    load4(img + (long long)max(yn - R - 1, 0) * pitch, qo);
+  };
+  if (y0 + 1 < y1) load_step(y0 + 1);
   for (int y = y0; y < y1; ++y) {
+    float pa[kChunks], pb[kChunks];
+    load_bounds_row(alpha, beta, sp, y, xo, g.O, W, lane, pa, pb);
     if (y > y0) {
-      const float* rin = img + (long long)min(y + R, H - 1) * pitch;
-      const float* rout = img + (long long)max(y - R - 1, 0) * pitch;
-      float qi[kV], qo[kV];
-      load4(rin, qi);
-      load4(rout, qo);
+      float ci[kV], co[kV];
 #pragma unroll
       for (int v = 0; v < kV; ++v) {
-        const double ui = (double)qi[v] - c;
-        const double uo = (double)qo[v] - c;
+        ci[v] = qi[v];
+        co[v] = qo[v];
+      }
+      if (y + 1 < y1) load_step(y + 1);
+#pragma unroll
+      for (int v = 0; v < kV; ++v) {
+        const double ui = (double)ci[v] - c;
+        const double uo = (double)co[v] - c;
         double pi = ui, po = uo;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -444,7 +478,7 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
       const double lo = (e - R - 1 >= 0) ? sh[wv][k][pidx(e - R - 1)] : 0.0;
       return (hi - lo) * inv_area;
     };
-    epilogue_row<N, TS, FUSED>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c,
+    epilogue_row<N, TS, FUSED>(sum_k, y, xo, g.O, W, H, R, img, pitch, pa, pb, sp, c,
                                cond_max, nullptr, inv_area, mom, plane, lane, fz);
     wave_sync();
   }
@@ -513,7 +547,9 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
       for (int dx = -R; dx <= R; ++dx) acc = fma(wts[dx + R], sh[wv][k][e + dx], acc);
       return acc * iz;
     };
-    epilogue_row<N, TS, false>(sum_k, y, xo, g.O, W, H, R, img, pitch, alpha, beta, sp, c,
+    float pa[kChunks], pb[kChunks];
+    load_bounds_row(alpha, beta, sp, y, xo, g.O, W, lane, pa, pb);
+    epilogue_row<N, TS, false>(sum_k, y, xo, g.O, W, H, R, img, pitch, pa, pb, sp, c,
                                cond_max, wts, iz * iz, mom, plane, lane, FuseArgs{});
     wave_sync();
   }
@@ -533,6 +569,7 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
 // direct convolution.
 constexpr int kTY = 4;   // output rows per tile
 constexpr int kCB = 2;   // adjacent output columns per thread in the horizontal phase
+constexpr int kPF = 8;   // input rows per prefetch chunk in the vertical phase
 
 template <int N, typename TS, bool FUSED>
 __global__ __launch_bounds__(256) void moments_gauss_tile(
@@ -570,28 +607,49 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   const double iz = 1.0 / z;
   const double c = origin;
 
-  // phase 1: vertical sums for padded column t
+  // phase 1: vertical sums for padded column t. The column's inputs are
+  // read in chunks of kPF rows, the next chunk's loads issued before the
+  // current chunk is used, so memory latency overlaps the arithmetic.
   if (t < E) {
-    const int cx = min(max(x0 - R + t, 0), W - 1);
+    const float* col = img + min(max(x0 - R + t, 0), W - 1);
+    const int n_in = kTY + 2 * R;
+    auto load_chunk = [&](int i0, float (&q)[kPF]) {
+#pragma unroll
+      for (int p = 0; p < kPF; ++p) {
+        const int i = min(i0 + p, n_in - 1);
+        q[p] = col[(long long)min(max(y0 - R + i, 0), H - 1) * pitch];
+      }
+    };
     double acc[kTY][N];
 #pragma unroll
     for (int r = 0; r < kTY; ++r)
 #pragma unroll
       for (int k = 0; k < N; ++k) acc[r][k] = 0.0;
-    for (int i = 0; i < kTY + 2 * R; ++i) {
-      const int yy = min(max(y0 - R + i, 0), H - 1);
-      const double u = (double)img[(long long)yy * pitch + cx] - c;
-      double pw[N];
-      pw[0] = u;
+    float qn[kPF];
+    load_chunk(0, qn);
+    for (int i0 = 0; i0 < n_in; i0 += kPF) {
+      float q[kPF];
 #pragma unroll
-      for (int k = 1; k < N; ++k) pw[k] = pw[k - 1] * u;
+      for (int p = 0; p < kPF; ++p) q[p] = qn[p];
+      if (i0 + kPF < n_in) load_chunk(i0 + kPF, qn);
 #pragma unroll
-      for (int r = 0; r < kTY; ++r) {
-        const int d = i - r;
-        if (d >= 0 && d <= 2 * R) {
-          const double wv = wts[d];
+      for (int p = 0; p < kPF; ++p) {
+        const int i = i0 + p;
+        if (i < n_in) {
+          const double u = (double)q[p] - c;
+          double pw[N];
+          pw[0] = u;
 #pragma unroll
-          for (int k = 0; k < N; ++k) acc[r][k] = fma(wv, pw[k], acc[r][k]);
+          for (int k = 1; k < N; ++k) pw[k] = pw[k - 1] * u;
+#pragma unroll
+          for (int r = 0; r < kTY; ++r) {
+            const int d = i - r;
+            if (d >= 0 && d <= 2 * R) {
+              const double wv = wts[d];
+#pragma unroll
+              for (int k = 0; k < N; ++k) acc[r][k] = fma(wv, pw[k], acc[r][k]);
+            }
+          }
         }
       }
     }
@@ -602,7 +660,10 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   }
   __syncthreads();
 
-  // phase 2: horizontal sums for kCB adjacent outputs of one row
+  // phase 2: horizontal sums for kCB = 2 adjacent outputs of one row. The
+  // (2 + 2R) LDS columns a thread spans are read as 16-byte pairs: the
+  // pairs of neighbouring lanes are contiguous, so the reads are free of
+  // bank conflicts (E, 2R and the thread's first column are even).
   const int groups = TX / kCB;
   const int r = t / groups, gq = t - r * groups;
   const bool active = r < kTY;
@@ -613,18 +674,22 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
     for (int v = 0; v < kCB; ++v)
 #pragma unroll
       for (int k = 0; k <= N; ++k) m4[v][k] = 0.0;
-    for (int j = 0; j < kCB + 2 * R; ++j) {
-      double val[N];
+    const double2* vs2 = reinterpret_cast<const double2*>(vsum);
+    for (int j = 0; j < kCB + 2 * R; j += 2) {
+      double2 val[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) val[k] = vsum[(k * kTY + r) * E + xl + j];
+      for (int k = 0; k < N; ++k) val[k] = vs2[((k * kTY + r) * E + xl + j) >> 1];
+      // column xl + j feeds output v = 0 at tap j and v = 1 at tap j - 1;
+      // column xl + j + 1 feeds v = 0 at tap j + 1 and v = 1 at tap j
+      const double w0 = wts[j];
+      const double w1 = j + 1 <= 2 * R ? wts[j + 1] : 0.0;
+      const double wm = j >= 1 ? wts[j - 1] : 0.0;
 #pragma unroll
-      for (int v = 0; v < kCB; ++v) {
-        const int d = j - v;
-        if (d >= 0 && d <= 2 * R) {
-          const double wv = wts[d];
-#pragma unroll
-          for (int k = 0; k < N; ++k) m4[v][k + 1] = fma(wv, val[k], m4[v][k + 1]);
-        }
+      for (int k = 0; k < N; ++k) {
+        m4[0][k + 1] = fma(w0, val[k].x, m4[0][k + 1]);
+        m4[0][k + 1] = fma(w1, val[k].y, m4[0][k + 1]);
+        m4[1][k + 1] = fma(wm, val[k].x, m4[1][k + 1]);
+        m4[1][k + 1] = fma(w0, val[k].y, m4[1][k + 1]);
       }
     }
   }
