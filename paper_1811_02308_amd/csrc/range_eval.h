@@ -106,14 +106,17 @@ __device__ __forceinline__ double range_eval(float a, float b, const double (&ak
     const double s = lam * dd * dd;
     const double E0 = exp_neg(s - A * A);    // exp(-lam t0^2) * e^s
     const double E1 = exp_neg(s - B * B);    // exp(-lam (1-t0)^2) * e^s
-    double diff;                          // (erf(B) - erf(A)) * e^s
-    if (A <= 0.0 && B >= 0.0) {
-      diff = 2.0 - erfcx(B) * E1 - erfcx(-A) * E0;
-    } else if (A > 0.0) {
-      diff = erfcx(A) * E0 - erfcx(B) * E1;
-    } else {
-      diff = erfcx(-B) * E1 - erfcx(-A) * E0;
-    }
+    // (erf(B) - erf(A)) * e^s from erfc of |A| and |B| (A < B):
+    //   A <= 0 <= B:  2 - erfc(B) - erfc(-A)
+    //   0 < A:        erfc(A) - erfc(B)
+    //   B < 0:        erfc(-B) - erfc(-A)
+    // with erfc(|z|) = erfcx(|z|) exp(-z^2), the e^s folded into E0 and E1.
+    // Two erfcx calls per pixel in every case, so a wave whose lanes fall in
+    // different cases does not run several inlined copies one after another.
+    const double X0 = erfcx(fabs(A)) * E0;
+    const double X1 = erfcx(fabs(B)) * E1;
+    const bool straddle = A <= 0.0 && B >= 0.0;
+    const double diff = (straddle ? 2.0 - X1 : (A > 0.0 ? -X1 : X1)) + (A > 0.0 ? X0 : -X0);
     const double i2l = 0.5 * rcp(lam);
     double Im2 = 0.5 * kSqrtPi * rcp(sl) * diff;     // I_0
     double Im1 = fma(t0, Im2, (E0 - E1) * i2l);      // I_1
