@@ -60,6 +60,39 @@ def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
     }
 
 
+def library_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over the library sources (file
+    names and contents of paper_1811_02308_amd/csrc/*.hip, *.h, *.cpp in
+    sorted order): identifies the kernels a stored counter reading was
+    taken with."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1811_02308_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, stage: str):
+    """HBM bytes per launch of the mixed path's `stage` kernel on `workload`
+    from profiles/traffic.md (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
+    the device-copy calibration), or None when no reading exists or the
+    library sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    if not os.path.exists(path):
+        return None
+    src = library_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) == 9 and cells[0] == workload and cells[1] == stage:
+                return int(float(cells[7])) if cells[8] == src else None
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +240,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(frac_h, 4)}
-    roof.update({"kernel": dom, "traffic": None, "launch_ms": round(stages[dom], 5),
+    roof.update({"kernel": dom, "traffic": measured_traffic(args.workload, dom),
+                 "launch_ms": round(stages[dom], 5),
                  "algorithmic_bytes": model[dom]["bytes"], "algorithmic_flops": model[dom]["flops"]})
 
     # ---------------------------------------------------------- CPU oracle baseline
