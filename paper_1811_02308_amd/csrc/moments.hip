@@ -576,7 +576,8 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R, int TX, double inv2s2,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
     TS* __restrict__ mom, long long plane, double cond_max, Batch bt, FuseArgs fz) {
-  extern __shared__ double vsum[];            // [N][kTY][E]
+  // [N][kTY][E]; 16-byte aligned for the pair reads of phase 2
+  extern __shared__ __attribute__((aligned(16))) double vsum[];
   img += blockIdx.z * bt.img;
   if (FUSED) {
     fz.theta += blockIdx.z * bt.img;
@@ -586,15 +587,20 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   alpha = byte_offset(alpha, blockIdx.z * bt.stack);
   beta = byte_offset(beta, blockIdx.z * bt.stack);
   mom = byte_offset(mom, blockIdx.z * bt.stack);
-  __shared__ double wts[2 * kRhoMax + 1];
+  // 1-D weights of taps -(kTY-1) .. 2R+kTY-1 (zero outside [0, 2R]), so
+  // the phases below apply every tap without a range test; wts = the taps
+  // 0 .. 2R
+  __shared__ double wext[2 * kRhoMax + 2 * kTY];
   __shared__ double origin;
+  double* const wts = wext + (kTY - 1);
   const int E = TX + 2 * R;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * kTY;
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1);
-  for (int i = t; i <= 2 * R; i += blockDim.x) {
-    const double d = (double)(i - R);
-    wts[i] = exp(-d * d * inv2s2);
+  for (int i = t; i < 2 * R + 2 * kTY - 1; i += blockDim.x) {
+    const int tap = i - (kTY - 1);
+    const double d = (double)(tap - R);
+    wext[i] = (tap >= 0 && tap <= 2 * R) ? exp(-d * d * inv2s2) : 0.0;
   }
   if (t < kWave) {
     const int y1 = min(H, y0 + kTY);
@@ -641,14 +647,12 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
           pw[0] = u;
 #pragma unroll
           for (int k = 1; k < N; ++k) pw[k] = pw[k - 1] * u;
+          // output row r takes tap i - r (a zero weight outside [0, 2R])
 #pragma unroll
           for (int r = 0; r < kTY; ++r) {
-            const int d = i - r;
-            if (d >= 0 && d <= 2 * R) {
-              const double wv = wts[d];
+            const double wv = wts[i - r];
 #pragma unroll
-              for (int k = 0; k < N; ++k) acc[r][k] = fma(wv, pw[k], acc[r][k]);
-            }
+            for (int k = 0; k < N; ++k) acc[r][k] = fma(wv, pw[k], acc[r][k]);
           }
         }
       }
@@ -682,8 +686,8 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
       // column xl + j feeds output v = 0 at tap j and v = 1 at tap j - 1;
       // column xl + j + 1 feeds v = 0 at tap j + 1 and v = 1 at tap j
       const double w0 = wts[j];
-      const double w1 = j + 1 <= 2 * R ? wts[j + 1] : 0.0;
-      const double wm = j >= 1 ? wts[j - 1] : 0.0;
+      const double w1 = wts[j + 1];      // 0 at j = 2R
+      const double wm = wts[j - 1];      // 0 at j = 0
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         m4[0][k + 1] = fma(w0, val[k].x, m4[0][k + 1]);
