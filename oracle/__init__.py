@@ -22,6 +22,8 @@ Contents
                (BF_adaptive1), (BF_adaptive2).
 ``mpref``      Algorithm 1 in 60-digit mpmath arithmetic for tiny images,
                used to pin the FP64 routes.
+``uniform``    the uniform-prior comparison variant of Sec. III-B (the
+               N = 0 estimator on [f, 2 fbar - f]).
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test
 against a closed form, an exact identity, brute force on tiny inputs or a
@@ -29,7 +31,8 @@ high-precision evaluation. The paper's printed PSNR values (Table 1, Fig. 3)
 need its test image, which is not available, so those numbers are
 **parity unpinned**; only their trend is checked.
 """
-from . import hilbert, spatial, integrals, fast, brute  # noqa: F401
+from . import hilbert, spatial, integrals, fast, brute, uniform  # noqa: F401
 from .fast import fast_abf, fast_abf_literal  # noqa: F401
 from .brute import brute_abf  # noqa: F401
 from .spatial import window_minmax  # noqa: F401
+from .uniform import uniform_prior_abf  # noqa: F401

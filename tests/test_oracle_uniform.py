@@ -1,0 +1,75 @@
+"""Pins for the uniform-prior comparison variant (oracle/uniform.py)."""
+import numpy as np
+import pytest
+from scipy.ndimage import gaussian_filter, uniform_filter
+from scipy.special import erf
+
+import oracle
+from oracle.uniform import uniform_prior_abf, window_mean
+from synth import rect_scene, smooth_field
+
+
+@pytest.fixture(scope="module")
+def scene():
+    return rect_scene(3, 48, 61, n_rect=5, noise=10, side_lo=8, side_hi=30)
+
+
+def test_window_mean_matches_library_filters(scene):
+    f = scene.astype(np.float64)
+    assert np.max(np.abs(window_mean(scene, "box", 3) - uniform_filter(f, 7, mode="nearest"))) < 1e-10
+    # sampled Gaussian of std R/3 truncated at radius R, normalised: scipy's
+    # filter with truncate = R / sigma_s uses the same radius and weights
+    g = gaussian_filter(f, sigma=2.0, truncate=3.0, mode="nearest")
+    assert np.max(np.abs(window_mean(scene, "gaussian", 6) - g)) < 1e-10
+
+
+def test_infinite_sigma_gives_window_mean(scene):
+    # lambda = 0: I_1 / I_0 = 1/2, so the output is the interval's midpoint,
+    # (f + 2 fbar - f) / 2 = fbar
+    out = uniform_prior_abf(scene, None, np.inf, "box", 2)
+    ref = uniform_filter(scene.astype(np.float64), 5, mode="nearest")
+    assert np.max(np.abs(out - ref)) < 1e-10
+
+
+def test_theta_equal_f_closed_form(scene):
+    # theta = f puts t0 at an end of [lo, hi]: t0 = 0 where f < fbar (then
+    # F = (1 - e^-lam) / (sqrt(pi lam) erf(sqrt(lam)))) and t0 = 1 where
+    # f > fbar (then 1 - F by symmetry)
+    sg = smooth_field(np.random.default_rng(2), *scene.shape, 5, 60)
+    out = uniform_prior_abf(scene, None, sg, "box", 3)
+    f = scene.astype(np.float64)
+    fb = uniform_filter(f, 7, mode="nearest")
+    other = 2 * fb - f
+    lo, hi = np.minimum(f, other), np.maximum(f, other)
+    d = hi - lo
+    live = d > 1e-6
+    lam = d[live] ** 2 / (2 * sg.astype(np.float64)[live] ** 2)
+    F = (1 - np.exp(-lam)) / (np.sqrt(np.pi * lam) * erf(np.sqrt(lam)))
+    F = np.where(f[live] < fb[live], F, 1 - F)
+    ref = lo[live] + d[live] * F
+    assert np.max(np.abs(out[live] - ref)) < 1e-9
+    assert np.array_equal(out[~live], f[~live]) or np.max(np.abs(out[~live] - f[~live])) < 1e-4
+
+
+def test_constant_image_and_pixels_argument(scene):
+    c = np.full((9, 11), 77.0, np.float32)
+    # fbar of a constant window equals f up to the rounding of the weighted
+    # sum, so the interval is a point or of width ~1e-14
+    assert np.max(np.abs(uniform_prior_abf(c, None, 20.0, "box", 2) - 77.0)) < 1e-12
+    ys, xs = np.array([0, 5, 47]), np.array([0, 30, 60])
+    full = uniform_prior_abf(scene, None, 25.0, "gaussian", 4)
+    assert np.allclose(uniform_prior_abf(scene, None, 25.0, "gaussian", 4, pixels=(ys, xs)),
+                       full[ys, xs], rtol=0, atol=1e-12)
+
+
+def test_paper_observations_classical_filter(scene):
+    """Sec. III-B, classical filter (theta = f, sigma = 40): the exact
+    interval [alpha, beta] beats the uniform prior's [f, 2 fbar - f] at
+    N = 0, and the PSNR against brute force rises with N."""
+    for R in (3, 5):
+        b = oracle.brute_abf(scene, None, 40.0, "box", R)
+        psnr = lambda g: 10 * np.log10(255.0 ** 2 / np.mean((g - b) ** 2))
+        u = psnr(uniform_prior_abf(scene, None, 40.0, "box", R))
+        ours = [psnr(oracle.fast_abf(scene, None, 40.0, "box", R, N)) for N in range(7)]
+        assert ours[0] > u
+        assert all(b_ > a_ for a_, b_ in zip(ours, ours[1:])), ours
