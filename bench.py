@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--parity-pixels", type=int, default=600)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device-to-device copy (counter calibration for profiles)")
+    ap.add_argument("--classical", action="store_true",
+                    help="classical-filter sweep over rho and N (timing and PSNR tables) instead of the headline")
     ap.add_argument("--serving-requests", type=int, default=0,
                     help="also run the serving stream (p50/p99 at 3 offered loads) with this many requests")
     args = ap.parse_args()
@@ -130,6 +132,8 @@ def main():
         torch.cuda.synchronize()
     if args.workload.startswith("texture"):
         return texture_bench(args)
+    if args.classical:
+        return classical_bench(args)
     wl = workload(args.workload)
     f, th, sg = wl["f"], wl["theta"], wl["sigma"]
     H, W = f.shape
@@ -307,6 +311,69 @@ def main():
         from paper_1811_02308_amd.serve import bench as serve_bench
         log("serving stream ...")
         res["serving"] = serve_bench(n=args.serving_requests, warm=max(10, args.serving_requests // 10))
+    print(json.dumps(res), flush=True)
+
+
+def classical_bench(args):
+    """Classical filter (theta = f, sigma = 40) on the 512 x 512 scene of
+    Sec. III-B's sweeps: GPU time of the fast path for rho in {3..11} and
+    N in {1, 3, 5} next to the GPU brute force (the structure of the paper's
+    timing table), and the PSNR against brute force for rho in {3, 5, 10},
+    N = 0..6, with the uniform-prior variant beside N = 0."""
+    import numpy as np
+    import torch
+
+    import paper_1811_02308_amd as abf
+    from synth import workload
+    wl = workload("classical512_box5_n5")
+    f = wl["f"]
+    H, W = f.shape
+    img = torch.from_numpy(f).cuda()
+    sg = torch.from_numpy(wl["sigma"]).cuda()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(5, min(args.steps, 50))
+    timing = {}
+    for R in (3, 5, 7, 9, 11):
+        row = {}
+        for N in (1, 3, 5):
+            for prec in ("mixed", "fp64"):
+                ws = torch.empty(abf.workspace_bytes(H, W, R, N, prec), dtype=torch.uint8, device="cuda")
+                out = torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64,
+                                  device="cuda")
+                row[f"N={N} {prec} ms"] = round(timed(
+                    lambda: abf.fast(img, sg, kernel="box", rho=R, N=N, precision=prec, out=out,
+                                     workspace=ws), reps), 5)
+        ob = torch.empty((H, W), dtype=torch.float64, device="cuda")
+        row["brute fp64 ms"] = round(timed(
+            lambda: abf.bruteforce(img, sg, kernel="box", rho=R, precision="fp64", out=ob), 3), 4)
+        timing[f"rho={R}"] = row
+        log(f"rho={R}: {row}")
+    psnr = {}
+    for R in (3, 5, 10):
+        b = abf.bruteforce(img, sg, kernel="box", rho=R, precision="fp64").cpu().numpy()
+        p = lambda g: round(float(10 * np.log10(255.0 ** 2 / np.mean(
+            (g.cpu().numpy().astype(np.float64) - b) ** 2))), 2)
+        psnr[f"rho={R}"] = {
+            "fp64": [p(abf.fast(img, sg, kernel="box", rho=R, N=N, precision="fp64")) for N in range(7)],
+            "mixed": [p(abf.fast(img, sg, kernel="box", rho=R, N=N, precision="mixed")) for N in range(7)],
+            "uniform_prior": p(abf.uniform_prior(img, sg, kernel="box", rho=R, precision="fp64")),
+        }
+        log(f"rho={R}: PSNR {psnr[f'rho={R}']}")
+    res = {"metric": "classical-filter sweep (theta = f, sigma = 40, box kernel)",
+           "config": {"workload": "classical512_box5_n5", "h": H, "w": W},
+           "timing_ms": timing, "psnr_db_vs_bruteforce": psnr,
+           "notes": "PSNR lists are N = 0..6; uniform_prior is the N = 0 estimator on [f, 2 fbar - f]"}
     print(json.dumps(res), flush=True)
 
 

@@ -179,6 +179,33 @@ abf_status abf_fast(const float* img, const float* theta, const float* sigma,
                     void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * abf_uniform_prior -- the uniform-prior comparison variant of Sec. III-B
+ * (classical filtering, Fig. 3 and the discussion beside Table 1): the
+ * N = 0 estimator of Algorithm 1 with the constant fitted on
+ * [f(i), 2 fbar(i) - f(i)] (ordered) instead of [alpha_i, beta_i], fbar the
+ * window mean under the same spatial kernel:
+ *   g^ = lo + (hi - lo) I_1 / I_0,  t0 = (theta - lo)/(hi - lo),
+ *   lambda = (hi - lo)^2 / (2 sigma^2);   g^ = f(i) where lo = hi.
+ * Builds an N = 1 moment stack in `workspace` (>= abf_workspace_bytes(h,
+ * w, rho, 1, precision)) and calls abf_range_uniform. Arguments and output
+ * types as for abf_fast.
+ *
+ * abf_range_uniform -- the same from a resident stack built with any
+ * N in [1, ABF_N_MAX] for this image, kernel and rho (fbar is recovered as
+ * (alpha+beta)/2 + (beta-alpha)/2 a~_1). img is always read (f(i) sets the
+ * interval); theta NULL means theta = img.
+ */
+abf_status abf_uniform_prior(const float* img, const float* theta, const float* sigma,
+                             int h, int w, long long pitch, int kernel_kind, double sigma_s,
+                             int rho, int precision, unsigned flags, void* out,
+                             long long out_pitch, void* workspace, size_t workspace_bytes,
+                             void* stream);
+abf_status abf_range_uniform(const void* stack, size_t stack_bytes, const float* img,
+                             const float* theta, const float* sigma, int h, int w,
+                             long long pitch, int N, int precision, unsigned flags, void* out,
+                             long long out_pitch, void* stream);
+
+/*
  * abf_bruteforce -- eqs. (BF_adaptive1), (BF_adaptive2) directly, O(rho^2)
  * per pixel; the plain reference the fast path is compared with.
  * ABF_PREC_FP64: FP64 arithmetic, double output. ABF_PREC_MIXED: FP32

@@ -19,7 +19,7 @@ import os
 __all__ = [
     "lib", "library_path", "fast", "bruteforce", "minmax", "moment_stack",
     "range_from_stack", "fast_batched", "minmax_into_stack", "stack_moments",
-    "fast_strided", "sigma_local_std", "moments_range", "workspace_bytes", "stack_bytes",
+    "fast_strided", "sigma_local_std", "moments_range", "uniform_prior", "range_uniform_from_stack", "workspace_bytes", "stack_bytes",
     "stack_planes", "Request", "KERNELS", "PRECISIONS", "ABFError",
 ]
 
@@ -76,6 +76,8 @@ def lib():
         "abf_stack_moments": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp], i),
         "abf_range": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
         "abf_moments_range": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, sz, vp, ll, vp], i),
+        "abf_uniform_prior": ([vp, vp, vp, i, i, ll, i, d, i, i, u, vp, ll, vp, sz, vp], i),
+        "abf_range_uniform": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
         "abf_fast": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, ll, vp, sz, vp], i),
         "abf_bruteforce": ([vp, vp, vp, i, i, ll, i, d, i, i, vp, ll, vp], i),
         "abf_batched_workspace_bytes": ([ctypes.POINTER(Request), i, i], sz),
@@ -310,6 +312,44 @@ def moments_range(img, stack, sigma, theta=None, kernel="box", rho=3, N=5, sigma
                                  float(sigma_s), int(rho), int(N), p, flags, _ptr(stack),
                                  stack.numel(), _ptr(out), out.stride(0), _stream(stream))
     _check(st, "abf_moments_range")
+    return out
+
+
+def uniform_prior(img, sigma, theta=None, kernel="box", rho=3, sigma_s=0.0, precision="mixed",
+                  clamp=True, out=None, workspace=None, stream=None):
+    """abf_uniform_prior: the uniform-prior comparison variant (N = 0 on
+    [f, 2 fbar - f])."""
+    torch = _torch()
+    img, sigma, theta = _plane(img, "img"), _plane(sigma, "sigma"), _plane(theta, "theta")
+    h, w = img.shape
+    pitch = _common_pitch(img, sigma, theta)
+    p = _prec(precision)
+    L = lib()
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+    if workspace is None:
+        workspace = _alloc_bytes(L.abf_workspace_bytes(h, w, int(rho), 1, p), img.device)
+    st = L.abf_uniform_prior(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
+                             float(sigma_s), int(rho), p, FLAG_CLAMP if clamp else 0, _ptr(out),
+                             out.stride(0), _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(st, "abf_uniform_prior")
+    return out
+
+
+def range_uniform_from_stack(stack, img, sigma, theta=None, N=5, precision="mixed", clamp=True,
+                             out=None, stream=None):
+    """abf_range_uniform: the uniform-prior variant from a resident stack."""
+    torch = _torch()
+    img, sigma, theta = _plane(img, "img"), _plane(sigma, "sigma"), _plane(theta, "theta")
+    h, w = img.shape
+    pitch = _common_pitch(img, sigma, theta)
+    p = _prec(precision)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+    st = lib().abf_range_uniform(_ptr(stack), stack.numel(), _ptr(img), _ptr(theta), _ptr(sigma),
+                                 h, w, pitch, int(N), p, FLAG_CLAMP if clamp else 0, _ptr(out),
+                                 out.stride(0), _stream(stream))
+    _check(st, "abf_range_uniform")
     return out
 
 

@@ -113,6 +113,13 @@ hipError_t launch_range(const float* alpha, const float* beta, long long sp,
                         int N, int prec, unsigned flags, void* out, long long opitch,
                         hipStream_t stream, const Batch& b = Batch());
 
+// Uniform-prior variant from a stack's bounds and first moment plane.
+hipError_t launch_range_uniform(const float* alpha, const float* beta, long long sp,
+                                const void* mom1, const float* img, long long ipitch,
+                                const float* theta_or_img, long long tpitch, const float* sigma,
+                                long long spitch, int h, int w, int prec, unsigned flags,
+                                void* out, long long opitch, hipStream_t stream);
+
 // sigma(i) = clamp(scale * std of f over the (2r+1)^2 clamp-to-edge window,
 // lo, hi), population standard deviation, FP64.
 hipError_t launch_sigma_std(const float* img, long long pitch, int h, int w, int r,

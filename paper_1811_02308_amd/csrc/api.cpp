@@ -260,6 +260,46 @@ abf_status abf_fast(const float* img, const float* theta, const float* sigma, in
                              precision, flags, ws, out, out_pitch, s, abf::Batch(), false);
 }
 
+abf_status abf_range_uniform(const void* stack, size_t stack_bytes, const float* img,
+                             const float* theta, const float* sigma, int h, int w, long long pitch,
+                             int N, int precision, unsigned flags, void* out, long long out_pitch,
+                             void* stream) {
+  if (!stack || !img || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || N < 1 ||
+      !prec_ok(precision))
+    return ABF_E_INVALID;
+  if (N > ABF_N_MAX) return ABF_E_UNSUPPORTED;
+  if (!aligned(stack) || stack_bytes < abf_stack_bytes(h, w, N, precision)) return ABF_E_WORKSPACE;
+  const long long sp = abf_stack_pitch(w);
+  const char* base = static_cast<const char*>(stack);
+  const float* alpha = reinterpret_cast<const float*>(base);
+  const float* beta = reinterpret_cast<const float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
+  const void* mom1 = base + abf_stack_plane_offset(h, w, N, precision, 2);
+  return hip_status(abf::launch_range_uniform(
+      alpha, beta, sp, mom1, img, pitch, theta ? theta : img, pitch, sigma, pitch, h, w,
+      precision == ABF_PREC_FP64 ? 0 : 1, flags & ABF_FLAG_CLAMP, out, out_pitch,
+      static_cast<hipStream_t>(stream)));
+}
+
+abf_status abf_uniform_prior(const float* img, const float* theta, const float* sigma, int h,
+                             int w, long long pitch, int kernel_kind, double sigma_s, int rho,
+                             int precision, unsigned flags, void* out, long long out_pitch,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  if (!img || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0 ||
+      !prec_ok(precision) || !kind_ok(kernel_kind) || !std::isfinite(sigma_s))
+    return ABF_E_INVALID;
+  if (rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (!workspace || !aligned(workspace) ||
+      workspace_bytes < abf_workspace_bytes(h, w, rho, 1, precision))
+    return ABF_E_WORKSPACE;
+  const size_t sb = abf_stack_bytes(h, w, 1, precision);
+  char* ws = static_cast<char*>(workspace);
+  abf_status st = abf_moment_stack(img, h, w, pitch, kernel_kind, sigma_s, rho, 1, precision, ws,
+                                   sb, ws + sb, workspace_bytes - sb, stream);
+  if (st != ABF_OK) return st;
+  return abf_range_uniform(ws, sb, img, theta, sigma, h, w, pitch, 1, precision, flags, out,
+                           out_pitch, stream);
+}
+
 abf_status abf_bruteforce(const float* img, const float* theta, const float* sigma, int h, int w,
                           long long pitch, int kernel_kind, double sigma_s, int rho,
                           int precision, void* out, long long out_pitch, void* stream) {

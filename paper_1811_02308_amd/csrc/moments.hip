@@ -591,7 +591,7 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   // the phases below apply every tap without a range test; wts = the taps
   // 0 .. 2R
   __shared__ double wext[2 * kRhoMax + 2 * kTY];
-  __shared__ double origin;
+  __shared__ double origin, inv_z;
   double* const wts = wext + (kTY - 1);
   const int E = TX + 2 * R;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * kTY;
@@ -605,12 +605,21 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   if (t < kWave) {
     const int y1 = min(H, y0 + kTY);
     const double c = wave_origin(alpha, beta, sp, y0, y1, x0, min(TX, W - x0), W, lane);
-    if (t == 0) origin = c;
+    // 1-D normalisation: the taps' sum, lane l adding taps l, l + 64, ...
+    double zp = 0.0;
+    for (int i = lane; i <= 2 * R; i += kWave) {
+      const double d = (double)(i - R);
+      zp += exp(-d * d * inv2s2);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) zp += __shfl_xor(zp, off, kWave);
+    if (t == 0) {
+      origin = c;
+      inv_z = 1.0 / zp;
+    }
   }
   __syncthreads();
-  double z = 0.0;
-  for (int i = 0; i <= 2 * R; ++i) z += wts[i];
-  const double iz = 1.0 / z;
+  const double iz = inv_z;
   const double c = origin;
 
   // phase 1: vertical sums for padded column t. The column's inputs are

@@ -75,6 +75,38 @@ __global__ __launch_bounds__(256) void range_kernel(
 }
 
 
+// Uniform-prior variant (Sec. III-B comparison): the N = 0 estimator on
+// [f(i), 2 fbar(i) - f(i)] (ordered), fbar the window mean under the
+// filter's spatial kernel, recovered from the stack's first Legendre
+// moment: fbar = mid + half a~_1 (a~_1 is the mean of z in [-1, 1]). A point
+// interval (f = fbar, which includes alpha = beta) gives f(i).
+template <typename TS, typename TO>
+__global__ __launch_bounds__(256) void uniform_kernel(
+    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    const TS* __restrict__ mom1, const float* __restrict__ img, long long ipitch,
+    const float* __restrict__ theta, long long tpitch, const float* __restrict__ sigma,
+    long long spitch, int H, int W, unsigned flags, TO* __restrict__ out, long long opitch,
+    GLArgs gl) {
+  constexpr bool kMixed = sizeof(TO) == 4;
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  const long long idx = (long long)y * sp + x;
+  const double a = alpha[idx], b = beta[idx];
+  const double f = img[(long long)y * ipitch + x] + 0.0f;
+  const double fbar = a == b ? a : fma(0.5 * (b - a), (double)mom1[idx], 0.5 * (a + b));
+  const double other = 2.0 * fbar - f;
+  const double lo = fmin(f, other), hi = fmax(f, other);
+  TO* o = out + (long long)y * opitch + x;
+  if (!(hi > lo)) {
+    *o = TO(f);
+    return;
+  }
+  const double ak[1] = {1.0};
+  *o = TO(range_eval<0, kMixed>(lo, hi, ak, (double)theta[(long long)y * tpitch + x],
+                                (double)sigma[(long long)y * spitch + x], flags, gl));
+}
+
 template <int N, typename TS, typename TO>
 hipError_t launch_t(const float* alpha, const float* beta, long long sp, const void* mom,
                     long long plane, const float* theta, long long tpitch, const float* sigma,
@@ -107,6 +139,24 @@ hipError_t dispatch(int N, const float* alpha, const float* beta, long long sp, 
 }
 
 }  // namespace
+
+hipError_t launch_range_uniform(const float* alpha, const float* beta, long long sp,
+                                const void* mom1, const float* img, long long ipitch,
+                                const float* theta_or_img, long long tpitch, const float* sigma,
+                                long long spitch, int h, int w, int prec, unsigned flags,
+                                void* out, long long opitch, hipStream_t stream) {
+  dim3 grid((w + 63) / 64, (h + 3) / 4);
+  const GLArgs gl = make_gl_args(prec != 0);
+  if (prec == 0)
+    hipLaunchKernelGGL((uniform_kernel<double, double>), grid, dim3(256), 0, stream, alpha, beta,
+                       sp, static_cast<const double*>(mom1), img, ipitch, theta_or_img, tpitch,
+                       sigma, spitch, h, w, flags, static_cast<double*>(out), opitch, gl);
+  else
+    hipLaunchKernelGGL((uniform_kernel<float, float>), grid, dim3(256), 0, stream, alpha, beta,
+                       sp, static_cast<const float*>(mom1), img, ipitch, theta_or_img, tpitch,
+                       sigma, spitch, h, w, flags, static_cast<float*>(out), opitch, gl);
+  return hipGetLastError();
+}
 
 hipError_t launch_range(const float* alpha, const float* beta, long long sp,
                         const void* mom, long long plane_elems,

@@ -74,17 +74,18 @@ __device__ __forceinline__ double rcp(double x) {
   return r;
 }
 
-// g^ = alpha + (beta - alpha) F for one pixel (alpha != beta). ak[k] =
-// (2k+1) a~_k with ak[0] = 1; th = theta, sg = sigma at the pixel.
+// g^ = a + (b - a) F for one pixel and the interval [a, b] (a < b; the
+// window bounds alpha, beta in Algorithm 1). ak[k] = (2k+1) a~_k with
+// ak[0] = 1; th = theta, sg = sigma at the pixel.
 // kMixed selects the mixed-precision thresholds, node count and FP32
 // quadrature exponentials.
 template <int N, bool kMixed>
-__device__ __forceinline__ double range_eval(float a, float b, const double (&ak)[N + 1], double th,
+__device__ __forceinline__ double range_eval(double a, double b, const double (&ak)[N + 1], double th,
                                              double sg, unsigned flags, const GLArgs& gl) {
   constexpr ShiftedLegTable SL{};
   constexpr LegTable LT{};
   constexpr int Q = kMixed ? kGLNodesMixed : kGLNodes;
-  const double da = a, delta = (double)b - da;
+  const double da = a, delta = b - da;
   const double t0 = (th - da) * rcp(delta);
   const double lam = isinf(sg) ? 0.0 : delta * delta * rcp(2.0 * sg * sg);
 

@@ -198,6 +198,18 @@ def _texture(seed: int = 1005, n_frames: int = 32, h: int = 1080, w: int = 1920)
 WORKLOADS["texture1080_box8_n6"] = _texture
 
 
+def _classical_512(seed: int = 1006):
+    f = rect_scene(seed, 512, 512)
+    return dict(f=f, theta=None, sigma=np.full((512, 512), 40.0, np.float32), kernel="box",
+                sigma_s=0.0, R=5, N=5)
+
+
+# classical filter (theta = f, sigma = sigma_0 = 40 everywhere) on a 512 x 512
+# rectangle scene: the setting of the paper's timing and PSNR sweeps over
+# rho and N (Sec. III-B); R and N here are the defaults, the sweep varies them
+WORKLOADS["classical512_box5_n5"] = _classical_512
+
+
 def workload(name: str, **kw):
     """Return the named workload dict (see ``WORKLOADS``)."""
     return WORKLOADS[name](**kw)
