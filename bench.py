@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--parity-pixels", type=int, default=600)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device-to-device copy (counter calibration for profiles)")
+    ap.add_argument("--paper-maps", action="store_true",
+                    help="the applications with the paper's parameter maps (sharpening, texture procedure)")
     ap.add_argument("--classical", action="store_true",
                     help="classical-filter sweep over rho and N (timing and PSNR tables) instead of the headline")
     ap.add_argument("--serving-requests", type=int, default=0,
@@ -134,6 +136,8 @@ def main():
         return texture_bench(args)
     if args.classical:
         return classical_bench(args)
+    if args.paper_maps:
+        return paper_maps_bench(args)
     wl = workload(args.workload)
     f, th, sg = wl["f"], wl["theta"], wl["sigma"]
     H, W = f.shape
@@ -374,6 +378,70 @@ def classical_bench(args):
            "config": {"workload": "classical512_box5_n5", "h": H, "w": W},
            "timing_ms": timing, "psnr_db_vs_bruteforce": psnr,
            "notes": "PSNR lists are N = 0..6; uniform_prior is the N = 0 estimator on [f, 2 fbar - f]"}
+    print(json.dumps(res), flush=True)
+
+
+def paper_maps_bench(args):
+    """The applications of Sec. IV with the paper's own parameter maps, all
+    on the GPU: sharpening of the 1024 x 1024 field (theta = 2 f - fbar over
+    the 31 x 31 window, sigma from |LoG|; Gaussian kernel R = 15, N = 6) and
+    the three-pass texture procedure (mRTV sigma, 0.8 sigma, sharpening) on
+    the 32 RGB 1920 x 1080 frames (box R = 8, N = 6)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1811_02308_amd as abf
+    from oracle import maps
+    from synth import workload
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps, (time.perf_counter() - t0) * 1e3 / reps
+
+    res = {"metric": "applications with the paper's parameter maps (Sec. IV)"}
+    sw = workload("sharpen1024_gauss15_n6")
+    f = torch.from_numpy(sw["f"]).cuda()
+    H, W = f.shape
+    ws = torch.empty(abf.workspace_bytes(H, W, 15, 6, "mixed"), dtype=torch.uint8, device="cuda")
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+
+    def sharpen():
+        th, sg = abf.sharpen_maps(f, radius=15, log_sigma=1.0, lo=5.0, hi=40.0, v_ref=20.0)
+        return abf.fast(f, sg[0], theta=th[0], kernel="gaussian", rho=15, N=6, sigma_s=5.0,
+                        out=out, workspace=ws), th, sg
+    (_, th, sg), dev_ms, wall_ms = timed(sharpen, max(5, min(args.steps, 50)))
+    rng = np.random.default_rng(3)
+    ys, xs = rng.integers(0, H, 300), rng.integers(0, W, 300)
+    ref = oracle.fast_abf(sw["f"], th[0].cpu().numpy(), sg[0].cpu().numpy(), "gaussian", 15, 6,
+                          sigma_s=5.0, pixels=(ys, xs))
+    rth, rsg = maps.sharpen_maps(sw["f"][:200, :200], 15, 1.0, 5.0, 40.0, 20.0)
+    res["sharpening"] = {
+        "workload": "sharpen1024 field, maps from the image, Gaussian R=15 N=6, mixed",
+        "ms_per_image": round(wall_ms, 4), "device_ms": round(dev_ms, 4),
+        "mpix_per_s": round(H * W / 1e6 / (wall_ms * 1e-3), 1),
+        "max_abs_err_vs_oracle": float(np.max(np.abs(out.cpu().numpy().astype(np.float64)[ys, xs] - ref))),
+        "maps_max_abs_err_vs_oracle_200x200": float(max(
+            np.max(np.abs(th[0].cpu().numpy()[:200, :200] - rth)[20:-20, 20:-20]),
+            np.max(np.abs(sg[0].cpu().numpy()[:200, :200] - rsg)[20:-20, 20:-20])))}
+    log("sharpening:", res["sharpening"])
+    tw = workload("texture1080_box8_n6")
+    n3, h, w = tw["frames"].shape
+    fr = torch.from_numpy(tw["frames"]).cuda().view(n3 // 3, 3, h, w)
+    for prec in ("mixed", "fp64"):
+        _, dev_ms, wall_ms = timed(lambda: abf.texture_filter_paper(fr, rho=8, N=6, precision=prec), 2)
+        res[f"texture_{prec}"] = {"ms_per_call": round(wall_ms, 3), "device_ms": round(dev_ms, 3),
+                                  "mpix_per_s": round(3 * n3 * h * w / 1e6 / (wall_ms * 1e-3), 1)}
+        log(f"texture {prec}:", res[f"texture_{prec}"])
+    res["config"] = {"texture": "32 RGB 1920x1080 frames, box R=8 N=6, 3 passes (mRTV sigma, 0.8 sigma, sharpening)"}
     print(json.dumps(res), flush=True)
 
 

@@ -262,6 +262,41 @@ abf_status abf_fast_strided(const float* img, const float* theta, const float* s
                             size_t workspace_bytes, void* stream);
 
 /*
+ * Parameter maps of the applications (Sec. IV). n images at image_stride
+ * (elements) in, maps at out_image_stride out (float32, row pitch
+ * out_pitch); every border clamp-to-edge; sums in FP64. The affine map of a
+ * measure v to sigma is sigma = hi - (hi - lo) min(v / v_ref, 1) (hi for
+ * v = 0, falling to lo at v >= v_ref; the paper specifies only that low
+ * values map to high sigma). lo <= hi, v_ref > 0.
+ *
+ * abf_sharpen_maps -- sharpening and noise removal (Sec. IV-A):
+ *   theta = f + zeta, zeta = f - fbar, fbar the mean of f over the
+ *   (2 radius + 1)^2 window; sigma = affine(|LoG * f|), the LoG being the sum
+ *   over both axes of the second derivative (x^2/s^4 - 1/s^2) g(x) of the
+ *   sampled Gaussian g of std s = log_sigma (radius round(4 s), normalised to
+ *   sum 1) along one axis times g along the other. radius and round(4 s) at
+ *   most 32.
+ * abf_mrtv_sigma -- texture filtering (Sec. IV-C): sigma = affine(mRTV),
+ *   mRTV = Delta max|grad f| / (sum|grad f| + eps) over the (2 radius + 1)^2
+ *   window, Delta = window max - window min of f, grad f by central
+ *   differences. radius at most 31, eps > 0.
+ * abf_grey -- 0.299 R + 0.587 G + 0.114 B of planar colour images (channel
+ *   planes channel_stride elements apart), the grey image the texture
+ *   application computes its maps on.
+ */
+abf_status abf_sharpen_maps(const float* img, int n, int h, int w, long long pitch,
+                            long long image_stride, int radius, double log_sigma, double lo,
+                            double hi, double v_ref, float* theta, float* sigma,
+                            long long out_pitch, long long out_image_stride, void* stream);
+abf_status abf_mrtv_sigma(const float* img, int n, int h, int w, long long pitch,
+                          long long image_stride, int radius, double eps, double lo, double hi,
+                          double v_ref, float* sigma, long long out_pitch,
+                          long long out_image_stride, void* stream);
+abf_status abf_grey(const float* rgb, int n, int h, int w, long long pitch,
+                    long long channel_stride, long long image_stride, float* out,
+                    long long out_pitch, long long out_image_stride, void* stream);
+
+/*
  * abf_sigma_local_std -- a per-pixel range width from local contrast for
  * texture filtering: sigma(i) = clamp(scale * sd(i), lo, hi), sd(i) the
  * population standard deviation of f over the clamp-to-edge window

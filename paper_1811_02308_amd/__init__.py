@@ -19,7 +19,8 @@ import os
 __all__ = [
     "lib", "library_path", "fast", "bruteforce", "minmax", "moment_stack",
     "range_from_stack", "fast_batched", "minmax_into_stack", "stack_moments",
-    "fast_strided", "sigma_local_std", "moments_range", "uniform_prior", "range_uniform_from_stack", "workspace_bytes", "stack_bytes",
+    "fast_strided", "sigma_local_std", "moments_range", "uniform_prior", "range_uniform_from_stack",
+    "sharpen_maps", "mrtv_sigma", "grey", "texture_filter_paper", "workspace_bytes", "stack_bytes",
     "stack_planes", "Request", "KERNELS", "PRECISIONS", "ABFError",
 ]
 
@@ -85,6 +86,9 @@ def lib():
         "abf_strided_workspace_bytes": ([i, i, i, i, i, i], sz),
         "abf_fast_strided": ([vp, vp, vp, i, i, i, ll, ll, i, d, i, i, i, u, vp, ll, ll, vp, sz, vp], i),
         "abf_sigma_local_std": ([vp, i, i, i, ll, ll, i, d, d, d, vp, ll, ll, vp], i),
+        "abf_sharpen_maps": ([vp, i, i, i, ll, ll, i, d, d, d, d, vp, vp, ll, ll, vp], i),
+        "abf_mrtv_sigma": ([vp, i, i, i, ll, ll, i, d, d, d, d, vp, ll, ll, vp], i),
+        "abf_grey": ([vp, i, i, i, ll, ll, ll, vp, ll, ll, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -459,3 +463,113 @@ def texture_filter(frames, passes=3, rho=8, N=6, radius=4, scale=3.0, lo=5.0, hi
                      out=outs[i % 2], workspace=ws, stream=stream)
         cur = outs[i % 2]
     return cur
+
+
+# ---------------------------------------------------------------- application maps (Sec. IV)
+def _out3(t, n, h, w, like):
+    torch = _torch()
+    if t is None:
+        return torch.empty((n, h, w), dtype=torch.float32, device=like.device)
+    t = _batch3(t, "out")
+    if tuple(t.shape) != (n, h, w):
+        raise ABFError("output maps must have the input batch's shape")
+    return t
+
+
+def sharpen_maps(img, radius=5, log_sigma=1.0, lo=5.0, hi=40.0, v_ref=20.0, theta=None,
+                 sigma=None, stream=None):
+    """abf_sharpen_maps: (theta, sigma) of the sharpening application for a
+    batch (n, h, w) or one image: theta = 2 f - fbar, sigma = affine(|LoG f|)."""
+    x = _batch3(img, "img")
+    n, h, w = x.shape
+    theta = _out3(theta, n, h, w, x)
+    sigma = _out3(sigma, n, h, w, x)
+    if theta.stride() != sigma.stride():
+        raise ABFError("theta and sigma outputs must share strides")
+    st = lib().abf_sharpen_maps(_ptr(x), n, h, w, x.stride(1), x.stride(0), int(radius),
+                                float(log_sigma), float(lo), float(hi), float(v_ref), _ptr(theta),
+                                _ptr(sigma), theta.stride(1), theta.stride(0), _stream(stream))
+    _check(st, "abf_sharpen_maps")
+    return theta, sigma
+
+
+def mrtv_sigma(img, radius=2, eps=1e-3, lo=5.0, hi=80.0, v_ref=20.0, out=None, stream=None):
+    """abf_mrtv_sigma: sigma = affine(mRTV) for a batch (n, h, w) or one image."""
+    x = _batch3(img, "img")
+    n, h, w = x.shape
+    out = _out3(out, n, h, w, x)
+    st = lib().abf_mrtv_sigma(_ptr(x), n, h, w, x.stride(1), x.stride(0), int(radius), float(eps),
+                              float(lo), float(hi), float(v_ref), _ptr(out), out.stride(1),
+                              out.stride(0), _stream(stream))
+    _check(st, "abf_mrtv_sigma")
+    return out
+
+
+def grey(rgb, out=None, stream=None):
+    """abf_grey: 0.299 R + 0.587 G + 0.114 B of planar colour images
+    (n, 3, h, w) or (3, h, w); returns (n, h, w)."""
+    torch = _torch()
+    if not isinstance(rgb, torch.Tensor) or rgb.device.type != "cuda" or rgb.dtype != torch.float32:
+        raise ABFError("rgb must be a float32 CUDA tensor")
+    if rgb.dim() == 3:
+        rgb = rgb.unsqueeze(0)
+    if rgb.dim() != 4 or rgb.shape[1] != 3 or rgb.stride(3) != 1:
+        raise ABFError("rgb must be (n, 3, h, w) with unit column stride")
+    n, _, h, w = rgb.shape
+    out = _out3(out, n, h, w, rgb)
+    st = lib().abf_grey(_ptr(rgb), n, h, w, rgb.stride(2), rgb.stride(1), rgb.stride(0), _ptr(out),
+                        out.stride(1), out.stride(0), _stream(stream))
+    _check(st, "abf_grey")
+    return out
+
+
+def texture_filter_paper(frames, rho=8, N=6, mrtv_radius=2, eps=1e-3, lo=5.0, hi=80.0,
+                         v_ref=20.0, shrink=0.8, log_sigma=1.0, sharpen_lo=5.0, sharpen_hi=40.0,
+                         sharpen_v_ref=20.0, precision="mixed", stream=None, keep=False):
+    """The texture-removal procedure of Sec. IV-C on planar colour frames
+    (n, 3, h, w), every step in the library's kernels:
+      sigma_1 = affine(mRTV) of the grey input (abf_grey, abf_mrtv_sigma);
+      pass 1: the fast filter, theta = f, sigma_1, channel by channel;
+      pass 2: the same on pass 1's output with sigma_1 scaled by `shrink`;
+      pass 3: sharpening (Sec. IV-A) of pass 2's output: theta = f + zeta per
+              channel, sigma from |LoG| of its grey image (abf_sharpen_maps).
+    The maps of all three channels of a frame are the grey image's (written
+    once per channel plane). Returns pass 3's output (n, 3, h, w), or with
+    ``keep`` a dict of every intermediate."""
+    torch = _torch()
+    if frames.dim() != 4 or frames.shape[1] != 3:
+        raise ABFError("frames must be (n, 3, h, w)")
+    n, _, h, w = frames.shape
+    x = frames.contiguous()
+    planes = x.view(n * 3, h, w)
+    p = _prec(precision)
+    ws = _alloc_bytes(lib().abf_strided_workspace_bytes(n * 3, h, w, rho, N, p), x.device)
+    sig3 = torch.empty((n, 3, h, w), dtype=torch.float32, device=x.device)
+    g0 = grey(x, stream=stream)
+    for c in range(3):
+        mrtv_sigma(g0, mrtv_radius, eps, lo, hi, v_ref, out=sig3[:, c], stream=stream)
+    y1 = fast_strided(planes, sig3.view(n * 3, h, w), kernel="box", rho=rho, N=N,
+                      precision=precision, workspace=ws, stream=stream)
+    y1f = y1 if y1.dtype == torch.float32 else y1.float()
+    sig3b = torch.empty_like(sig3)
+    for c in range(3):
+        mrtv_sigma(g0, mrtv_radius, eps, shrink * lo, shrink * hi, v_ref, out=sig3b[:, c],
+                   stream=stream)
+    y2 = fast_strided(y1f, sig3b.view(n * 3, h, w), kernel="box", rho=rho, N=N,
+                      precision=precision, workspace=ws, stream=stream)
+    y2f = y2 if y2.dtype == torch.float32 else y2.float()
+    th, scratch = sharpen_maps(y2f, rho, log_sigma, sharpen_lo, sharpen_hi, sharpen_v_ref,
+                               stream=stream)
+    g2 = grey(y2f.view(n, 3, h, w), stream=stream)
+    sig3c = torch.empty_like(sig3)
+    for c in range(3):
+        sharpen_maps(g2, rho, log_sigma, sharpen_lo, sharpen_hi, sharpen_v_ref,
+                     theta=scratch.view(n, 3, h, w)[:, c], sigma=sig3c[:, c], stream=stream)
+    y3 = fast_strided(y2f, sig3c.view(n * 3, h, w), theta=th, kernel="box", rho=rho, N=N,
+                      precision=precision, workspace=ws, stream=stream)
+    out = y3.view(n, 3, h, w)
+    if keep:
+        return dict(grey0=g0, sigma1=sig3, pass1=y1.view(n, 3, h, w), sigma2=sig3b,
+                    pass2=y2.view(n, 3, h, w), theta3=th.view(n, 3, h, w), grey2=g2,
+                    sigma3=sig3c, pass3=out)
+    return out

@@ -126,6 +126,18 @@ hipError_t launch_sigma_std(const float* img, long long pitch, int h, int w, int
                             double scale, double lo, double hi, float* out, long long opitch,
                             hipStream_t stream, const Batch& b = Batch());
 
+// Application parameter maps (maps.hip). maps_params_ok: window radius r
+// and LoG std s within the kernels' halo limit.
+bool maps_params_ok(int r, double s);
+hipError_t launch_sharpen_maps(const float* img, long long pitch, int h, int w, int r, double s,
+                               double lo, double hi, double v_ref, float* theta, float* sigma,
+                               long long op, hipStream_t stream, const Batch& b);
+hipError_t launch_mrtv_sigma(const float* img, long long pitch, int h, int w, int r, double eps,
+                             double lo, double hi, double v_ref, float* sigma, long long op,
+                             hipStream_t stream, const Batch& b);
+hipError_t launch_grey(const float* rgb, long long pitch, long long cstride, int h, int w,
+                       float* out, long long op, hipStream_t stream, const Batch& b);
+
 hipError_t launch_brute(const float* img, const float* theta, const float* sigma,
                         long long pitch, int h, int w, int kernel_kind, double sigma_s,
                         int rho, int prec, void* out, long long opitch,

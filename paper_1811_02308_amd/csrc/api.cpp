@@ -384,6 +384,65 @@ abf_status abf_fast_strided(const float* img, const float* theta, const float* s
                              precision, flags, base, out, out_pitch, s, b, false);
 }
 
+// shared checks of the strided map entry points
+static bool strided_ok(const float* img, const void* out, int n, int h, int w, long long pitch,
+                       long long image_stride, long long out_pitch, long long out_image_stride) {
+  return img && out && shape_ok(h, w, pitch) && out_pitch >= w && n >= 1 && n <= 65535 &&
+         (n == 1 || (image_stride >= pitch * (long long)(h - 1) + w &&
+                     out_image_stride >= out_pitch * (long long)(h - 1) + w));
+}
+
+static abf::Batch map_batch(int n, long long image_stride, long long out_image_stride) {
+  abf::Batch b;
+  b.n = n;
+  b.img = n > 1 ? image_stride : 0;
+  b.out = n > 1 ? out_image_stride : 0;
+  return b;
+}
+
+static bool affine_ok(double lo, double hi, double v_ref) {
+  return std::isfinite(lo) && std::isfinite(hi) && lo <= hi && v_ref > 0.0 && std::isfinite(v_ref);
+}
+
+abf_status abf_sharpen_maps(const float* img, int n, int h, int w, long long pitch,
+                            long long image_stride, int radius, double log_sigma, double lo,
+                            double hi, double v_ref, float* theta, float* sigma,
+                            long long out_pitch, long long out_image_stride, void* stream) {
+  if (!sigma || !strided_ok(img, theta, n, h, w, pitch, image_stride, out_pitch, out_image_stride) ||
+      radius < 0 || !(log_sigma > 0.0) || !affine_ok(lo, hi, v_ref))
+    return ABF_E_INVALID;
+  if (!abf::maps_params_ok(radius, log_sigma)) return ABF_E_UNSUPPORTED;
+  return hip_status(abf::launch_sharpen_maps(img, pitch, h, w, radius, log_sigma, lo, hi, v_ref,
+                                             theta, sigma, out_pitch,
+                                             static_cast<hipStream_t>(stream),
+                                             map_batch(n, image_stride, out_image_stride)));
+}
+
+abf_status abf_mrtv_sigma(const float* img, int n, int h, int w, long long pitch,
+                          long long image_stride, int radius, double eps, double lo, double hi,
+                          double v_ref, float* sigma, long long out_pitch,
+                          long long out_image_stride, void* stream) {
+  if (!strided_ok(img, sigma, n, h, w, pitch, image_stride, out_pitch, out_image_stride) ||
+      radius < 0 || !(eps > 0.0) || !affine_ok(lo, hi, v_ref))
+    return ABF_E_INVALID;
+  if (!abf::maps_params_ok(radius + 1, 1.0)) return ABF_E_UNSUPPORTED;
+  return hip_status(abf::launch_mrtv_sigma(img, pitch, h, w, radius, eps, lo, hi, v_ref, sigma,
+                                           out_pitch, static_cast<hipStream_t>(stream),
+                                           map_batch(n, image_stride, out_image_stride)));
+}
+
+abf_status abf_grey(const float* rgb, int n, int h, int w, long long pitch,
+                    long long channel_stride, long long image_stride, float* out,
+                    long long out_pitch, long long out_image_stride, void* stream) {
+  if (!strided_ok(rgb, out, n, h, w, pitch, image_stride, out_pitch, out_image_stride) ||
+      channel_stride < pitch * (long long)(h - 1) + w ||
+      (n > 1 && image_stride < 2 * channel_stride + pitch * (long long)(h - 1) + w))
+    return ABF_E_INVALID;
+  return hip_status(abf::launch_grey(rgb, pitch, channel_stride, h, w, out, out_pitch,
+                                     static_cast<hipStream_t>(stream),
+                                     map_batch(n, image_stride, out_image_stride)));
+}
+
 abf_status abf_sigma_local_std(const float* img, int n, int h, int w, long long pitch,
                                long long image_stride, int radius, double scale, double lo,
                                double hi, float* out, long long out_pitch,
