@@ -38,18 +38,25 @@ __device__ __forceinline__ double affine_sigma(double v, double lo, double hi, d
   return hi - (hi - lo) * fmin(v / v_ref, 1.0);
 }
 
-// theta = 2 f - fbar and sigma = affine(|LoG f|); h = max(r, q).
+// theta = 2 f - fbar and sigma = affine(|LoG f|); h = max(r, q). Both are
+// separable: phase A forms, for every padded row of the tile and every
+// output column, the row's box sum over 2r+1 columns and its convolutions
+// with g and d2 over 2q+1 columns; phase B sums those down the columns.
 __global__ __launch_bounds__(kMT* kMT) void sharpen_maps_kernel(
     const float* __restrict__ img, long long pitch, int H, int W, int r, double s, int q,
     double lo, double hi, double v_ref, float* __restrict__ theta, float* __restrict__ sigma,
     long long op, Batch bt) {
-  extern __shared__ float tile[];
+  extern __shared__ double rows[];                   // hbox, hg, hd2: E x kMT each; then the tile
   __shared__ double g[2 * kMapsHaloMax + 1], d2[2 * kMapsHaloMax + 1];
   img += blockIdx.z * bt.img;
   theta += blockIdx.z * bt.out;
   sigma += blockIdx.z * bt.out;
   const int h = max(r, q);
   const int E = kMT + 2 * h;
+  double* hbox = rows;
+  double* hg = rows + E * kMT;
+  double* hd2 = rows + 2 * E * kMT;
+  float* tile = reinterpret_cast<float*>(rows + 3 * E * kMT);
   const int bx = blockIdx.x * kMT, by = blockIdx.y * kMT;
   if (threadIdx.x == 0) {
     // sampled Gaussian normalised to sum 1, and its second derivative
@@ -67,22 +74,35 @@ __global__ __launch_bounds__(kMT* kMT) void sharpen_maps_kernel(
   }
   load_tile(img, pitch, H, W, bx, by, h, tile);
   __syncthreads();
+  // phase A: item = (padded row, output column), columns fastest
+  for (int it = threadIdx.x; it < E * kMT; it += kMT * kMT) {
+    const int row = it / kMT, col = it - row * kMT;
+    const float* t = tile + row * E + col + h;
+    double sb = 0.0, sg_ = 0.0, sd = 0.0;
+    for (int dx = -r; dx <= r; ++dx) sb += (double)t[dx];
+    for (int dx = -q; dx <= q; ++dx) {
+      const double v = t[dx];
+      sg_ = fma(g[dx + q], v, sg_);
+      sd = fma(d2[dx + q], v, sd);
+    }
+    hbox[it] = sb;
+    hg[it] = sg_;
+    hd2[it] = sd;
+  }
+  __syncthreads();
   const int tx = threadIdx.x % kMT, ty = threadIdx.x / kMT;
   const int x = bx + tx, y = by + ty;
   if (x >= W || y >= H) return;
-  // window mean, rows then columns as in the oracle's offset loop
   double sum = 0.0;
-  for (int dy = -r; dy <= r; ++dy)
-    for (int dx = -r; dx <= r; ++dx) sum += (double)tile[(ty + h + dy) * E + tx + h + dx];
+  for (int dy = -r; dy <= r; ++dy) sum += hbox[(ty + h + dy) * kMT + tx];
+  double L = 0.0;
+  for (int dy = -q; dy <= q; ++dy) {
+    const int k = (ty + h + dy) * kMT + tx;
+    L = fma(d2[dy + q], hg[k], fma(g[dy + q], hd2[k], L));
+  }
   const double w = 2.0 * r + 1.0;
   const double f = tile[(ty + h) * E + tx + h];
   const double fbar = sum / (w * w);
-  double L = 0.0;
-  for (int dy = -q; dy <= q; ++dy)
-    for (int dx = -q; dx <= q; ++dx) {
-      const double k = d2[dy + q] * g[dx + q] + g[dy + q] * d2[dx + q];
-      L = fma(k, (double)tile[(ty + h + dy) * E + tx + h + dx], L);
-    }
   theta[(long long)y * op + x] = (float)(2.0 * f - fbar);
   sigma[(long long)y * op + x] = (float)affine_sigma(fabs(L), lo, hi, v_ref);
 }
@@ -159,8 +179,9 @@ hipError_t launch_sharpen_maps(const float* img, long long pitch, int h, int w, 
                                long long op, hipStream_t stream, const Batch& b) {
   const int q = (int)(4.0 * s + 0.5);
   const int halo = r > q ? r : q;
+  const int E = kMT + 2 * halo;
   dim3 grid((w + kMT - 1) / kMT, (h + kMT - 1) / kMT, b.n);
-  const size_t lds = (size_t)(kMT + 2 * halo) * (kMT + 2 * halo) * sizeof(float);
+  const size_t lds = (size_t)3 * E * kMT * sizeof(double) + (size_t)E * E * sizeof(float);
   hipLaunchKernelGGL(sharpen_maps_kernel, grid, dim3(kMT * kMT), lds, stream, img, pitch, h, w, r,
                      s, q, lo, hi, v_ref, theta, sigma, op, b);
   return hipGetLastError();
