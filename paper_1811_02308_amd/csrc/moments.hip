@@ -732,6 +732,194 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   }
 }
 
+// Gaussian kernel on the matrix cores (R <= 16): the separable weighted sums
+// are banded matrix products done with v_mfma_f64_16x16x4f64 (FP64 in,
+// FP64 accumulate). A wave owns a strip of 16 output columns and walks down
+// it in 16-row blocks. For a 16-row block of the image, the horizontal pass
+//   H_k[r][c] = sum_j (f - c0)^k[r][x0 - R + j] w(j - c),  c < 16,
+// is one product per power k: A = the pixels' powers (row r = lane & 15,
+// column j = 4 s + (lane >> 4) of K-step s, each lane loading one pixel per
+// step), B = the band of weights. Its result stays in the MFMA output
+// layout, where the 4 registers of a lane hold rows 4 v + (lane >> 4) of
+// column lane & 15; each register v is exactly the B operand of a K-step
+// over those 4 rows, so the vertical pass
+//   G_k[r'][c] = sum_rows w(row - r' + R) H_k[row][c]
+// over the three row blocks b-1, b, b+1 (R <= 16) needs no data movement.
+// The wave keeps the three blocks' H in registers and computes one new
+// block per output block. G is the window moment of (f - c0)^k (weights
+// normalised to sum 1); the epilogue is the other kernels' (shift, Legendre
+// basis, exact recompute of ill-conditioned pixels).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaRMax = 16;
+constexpr int kKHMax = (16 + 2 * kMfmaRMax + 3) / 4;   // K-steps of the horizontal pass
+
+__device__ __forceinline__ mfma_d4 mfma16(double a, double b, mfma_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int N, typename TS>
+__global__ __launch_bounds__(kWaves * kWave, N <= 6 ? 2 : 1) void moments_gauss_mfma(
+    const float* __restrict__ img, long long pitch, int H, int W, int R, double inv2s2,
+    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    TS* __restrict__ mom, long long plane, int TH, int n_strips, int n_segs, double cond_max,
+    Batch bt) {
+  __shared__ double wts[2 * kMfmaRMax + 1];          // 1-D weights, normalised to sum 1
+  // per-lane MFMA weight fragments, the same for every wave: fh[s][lane] the
+  // horizontal pass's B operand of K-step s, fv[t][lane] the vertical pass's
+  // A operand for row block b + t / 4 - 1 and register t % 4
+  __shared__ double fh[kKHMax][kWave];
+  __shared__ double fv[12][kWave];
+  img += blockIdx.y * bt.img;
+  alpha = byte_offset(alpha, blockIdx.y * bt.stack);
+  beta = byte_offset(beta, blockIdx.y * bt.stack);
+  mom = byte_offset(mom, blockIdx.y * bt.stack);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int m = lane >> 4, q = lane & 15;
+  if (threadIdx.x < kWave) {
+    double zp = 0.0;
+    for (int i = lane; i <= 2 * R; i += kWave) {
+      const double d = (double)(i - R);
+      zp += exp(-d * d * inv2s2);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) zp += __shfl_xor(zp, off, kWave);
+    for (int i = lane; i <= 2 * R; i += kWave) {
+      const double d = (double)(i - R);
+      wts[i] = exp(-d * d * inv2s2) / zp;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    // horizontal: input column 4 s + m of the K-step feeds output column q
+    // with tap 4 s + m - q (zero off the band, which covers s >= KH too)
+#pragma unroll
+    for (int s = 0; s < kKHMax; ++s) {
+      const int d = 4 * s + m - q;
+      fh[s][lane] = (d >= 0 && d <= 2 * R) ? wts[d] : 0.0;
+    }
+    // vertical: output row q takes input row 16 dl + 4 v + m with tap
+    // 16 dl + 4 v + m - q + R
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+      const int d = 16 * (t / 4 - 1) + 4 * (t % 4) + m - q + R;
+      fv[t][lane] = (d >= 0 && d <= 2 * R) ? wts[d] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int gw = blockIdx.x * kWaves + wv;
+  if (gw >= n_strips * n_segs) return;
+  const int strip = gw % n_strips, seg = gw / n_strips;
+  const int x0 = strip * 16;
+  const int y0 = seg * TH;                           // a multiple of 16
+  const int y1 = min(H, y0 + TH);
+  const int KH = (16 + 2 * R + 3) / 4;
+  const double c = wave_origin(alpha, beta, sp, y0, y1, x0, 16, W, lane);
+  const int xc = x0 - R + m;
+
+  // pixels of the 16-row block bb this lane feeds to the horizontal pass
+  // (rows and columns clamped to the image)
+  auto hload = [&](int bb, float (&v)[kKHMax]) {
+    const float* row = img + (long long)min(max(16 * bb + q, 0), H - 1) * pitch;
+#pragma unroll
+    for (int s = 0; s < kKHMax; ++s)
+      v[s] = (s < KH) ? row[min(max(xc + 4 * s, 0), W - 1)] : 0.0f;
+  };
+  // horizontal pass of a 16-row block from its loaded pixels
+  auto hpass = [&](const float (&v)[kKHMax], mfma_d4 (&Hk)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) Hk[k] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kKHMax; ++s) {
+      if (s < KH) {
+        const double wf = fh[s][lane];
+        const double u = (double)v[s] - c;
+        double p = u;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          Hk[k] = mfma16(p, wf, Hk[k]);
+          p *= u;
+        }
+      }
+    }
+  };
+  // acc += (vertical weights of row-block offset t0 / 4 - 1) x Hk; a K-step
+  // whose 4 rows lie outside every output row's window [-R, 15 + R] has only
+  // zero weights and is skipped
+  auto vpass = [&](int t0, const mfma_d4 (&Hk)[N], mfma_d4 (&acc)[N]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row0 = 16 * (t0 / 4 - 1) + 4 * v;          // first row of the K-step
+      if (row0 + 3 < -R || row0 > 15 + R) continue;
+      const double wf = fv[t0 + v][lane];
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc[k] = mfma16(wf, Hk[k][v], acc[k]);
+    }
+  };
+  // the window moments of output block b are P_b + Wv(+1) H_{b+1} with the
+  // partial sum P_b = Wv(-1) H_{b-1} + Wv(0) H_b carried from the previous
+  // step; Hc = H_b, Hn receives H_{b+1}, pix holds block b+1's pixels and is
+  // refilled with block b+2's
+  float pix[kKHMax];
+  mfma_d4 P[N];
+  auto step = [&](int b, const mfma_d4 (&Hc)[N], mfma_d4 (&Hn)[N]) {
+    // this block's window bounds, loaded ahead of the epilogue
+    float pa[4], pb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int y = min(16 * b + 4 * v + m, y1 - 1), x = min(x0 + q, W - 1);
+      pa[v] = alpha[(long long)y * sp + x];
+      pb[v] = beta[(long long)y * sp + x];
+    }
+    hpass(pix, Hn);
+    hload(b + 2, pix);
+    vpass(8, Hn, P);                                 // P = moments of block b
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int y = 16 * b + 4 * v + m, x = x0 + q;
+      const bool valid = y < y1 && x < W;
+      const long long idx = (long long)(valid ? y : y0) * sp + (valid ? x : x0);
+      float a = 0.f, bb = 0.f;
+      bool bad = false;
+      if (valid) {
+        double mm[N + 1];
+        mm[0] = 1.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) mm[k + 1] = P[k][v];
+        a = pa[v];
+        bb = pb[v];
+        bad = legendre_from_moments<N>(mm, a, bb, c, cond_max);
+        if (!bad) finish_pixel<N, TS, false>(mm, a, bb, y, x, idx, mom, plane, FuseArgs{});
+      }
+      const unsigned long long mask = __ballot(valid && bad);
+      if (mask)
+        recompute_flagged<N, TS, false>(mask, valid && bad, y, x, a, bb, img, pitch, H, W, R,
+                                        wts, 1.0, mom, plane, sp, lane, FuseArgs{});
+    }
+    // partial sum of block b + 1
+#pragma unroll
+    for (int k = 0; k < N; ++k) P[k] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    vpass(0, Hc, P);
+    vpass(4, Hn, P);
+  };
+  const int b0 = y0 / 16, b1 = (y1 + 15) / 16;
+  mfma_d4 HA[N], HB[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) P[k] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  hload(b0 - 1, pix);
+  hpass(pix, HA);
+  vpass(0, HA, P);
+  hload(b0, pix);
+  hpass(pix, HB);
+  vpass(4, HB, P);
+  hload(b0 + 1, pix);
+  // two alternating buffers for H_b and H_{b+1}
+  for (int b = b0; b < b1; b += 2) {
+    step(b, HB, HA);
+    if (b + 1 < b1) step(b + 1, HA, HB);
+  }
+}
+
 // Output columns per Gaussian tile: at most 128, with the LDS tile
 // kTY x (TX + 2R) x N doubles within 64 KiB; 0 if R is too large.
 int gauss_tile_tx(int R, int N) {
@@ -824,6 +1012,25 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     return hipGetLastError();
   }
   const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
+  // the matrix-core kernel is the faster one for wide windows on large
+  // images (measured: at 2048^2 and 4096^2 with 8 <= R <= 16 it takes 0.8-0.95
+  // of the tile kernel's time; at 1024^2 they tie, below that it is slower)
+  if (!fs && R <= kMfmaRMax && R >= 8 && (long long)h * w >= (1LL << 22)) {
+    // strips of 16 columns; segment height a multiple of 16, chosen so the
+    // grid has about two waves per SIMD (8 per CU)
+    const int n_strips = (w + 15) / 16;
+    const long long target = 4LL * device_cus();
+    long long segs = (target + n_strips - 1) / n_strips;
+    int TH = (int)(((h + segs - 1) / segs + 15) / 16 * 16);
+    if (TH < 32) TH = 32;
+    const int n_segs = (h + TH - 1) / TH;
+    const int n_waves = n_strips * n_segs;
+    dim3 grid((n_waves + kWaves - 1) / kWaves, b.n);
+    hipLaunchKernelGGL((moments_gauss_mfma<N, TS>), grid, dim3(kWaves * kWave), 0, stream, img,
+                       pitch, h, w, R, 1.0 / (2.0 * s * s), alpha, beta, sp, mom, plane, TH,
+                       n_strips, n_segs, cond_max, b);
+    return hipGetLastError();
+  }
   const int tx = gauss_tile_tx(R, N);
   if (tx > 0) {
     dim3 tg((w + tx - 1) / tx, (h + kTY - 1) / kTY, b.n);
@@ -876,7 +1083,12 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w,
 }
 
 bool moments_fusable(int kernel_kind, int rho, int N) {
-  return N >= 1 && (kernel_kind == 0 || gauss_tile_tx(rho, N) > 0);
+  // The fused variant has no matrix-core form; where abf_stack_moments may
+  // use the matrix-core kernel (Gaussian, 8 <= rho <= 16) the fused call
+  // takes the stack path, so that its output stays identical to
+  // abf_stack_moments + abf_range.
+  return N >= 1 &&
+         (kernel_kind == 0 || ((rho < 8 || rho > kMfmaRMax) && gauss_tile_tx(rho, N) > 0));
 }
 
 }  // namespace abf

@@ -295,3 +295,23 @@ def test_fused_equals_stack_path(torch, abf, precision, kernel, R, N):
     for p, q in zip(abf.stack_planes(st, *f.shape, N, precision)[2],
                     abf.stack_planes(st2, *f.shape, N, precision)[2]):
         assert torch.equal(p, q)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("R,N", [(12, 8), (8, 5), (16, 6)])
+def test_fast_gaussian_large_image_sampled(torch, abf, precision, R, N):
+    """Wide Gaussian windows on a 2048 x 2048 image (the size at which the
+    moment stage runs on the matrix cores), sampled pixels against the oracle,
+    edges, corners and the last partial 16-row block included."""
+    from synth import gauss_field
+    f = gauss_field(77 + R, 2048, 2040)
+    sg = smooth_field(np.random.default_rng(R), *f.shape, 5, 60)
+    th = (f + smooth_field(np.random.default_rng(R + 1), *f.shape, -20, 20)).astype(np.float32)
+    wl = dict(f=f, theta=th, sigma=sg, kernel="gaussian", R=R, N=N, sigma_s=R / 3.0)
+    out = run_fast(torch, abf, wl, precision)
+    ys, xs = sample_pixels(*f.shape, n=400, seed=R)
+    ys = np.concatenate([ys, [2047, 2047, 2040, 15, 16]])
+    xs = np.concatenate([xs, [2039, 1000, 7, 2039, 0]])
+    ref = oracle.fast_abf(f, th, sg, "gaussian", R, N, sigma_s=R / 3.0, pixels=(ys, xs))
+    err = np.abs(out[ys, xs] - ref)
+    assert np.max(err) < TOL[precision], np.max(err)
