@@ -60,19 +60,25 @@ def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
     }
 
 
-def library_source_hash() -> str:
-    """First 16 hex digits of the SHA-256 over the library sources (file
-    names and contents of paper_1811_02308_amd/csrc/*.hip, *.h, *.cpp in
-    sorted order): identifies the kernels a stored counter reading was
-    taken with."""
-    import glob
+# The sources each timed stage's kernel is compiled from (its own file and
+# the headers that file includes).
+STAGE_SOURCES = {
+    "minmax": ("minmax.hip", "abf_internal.h"),
+    "moments": ("moments.hip", "range_eval.h", "abf_internal.h"),
+    "range": ("range.hip", "range_eval.h", "abf_internal.h"),
+}
+
+
+def stage_source_hash(stage: str) -> str:
+    """First 16 hex digits of the SHA-256 over the sources of one stage's
+    kernel (file names and contents, in the order of STAGE_SOURCES):
+    identifies the kernel a stored counter reading was taken with."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1811_02308_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for name in STAGE_SOURCES[stage]:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1811_02308_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -80,11 +86,11 @@ def measured_traffic(workload: str, stage: str):
     """HBM bytes per launch of the mixed path's `stage` kernel on `workload`
     from profiles/traffic.md (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
     the device-copy calibration), or None when no reading exists or the
-    library sources changed since it was taken."""
+    stage's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.md")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or stage not in STAGE_SOURCES:
         return None
-    src = library_source_hash()
+    src = stage_source_hash(stage)
     with open(path) as fh:
         for line in fh:
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
@@ -113,7 +119,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the filter runs on a single GPU (per-GPU sharding is described, not implemented); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

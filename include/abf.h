@@ -97,7 +97,7 @@ size_t abf_workspace_bytes(int h, int w, int rho, int N, int precision);
 
 /*
  * abf_minmax -- eq. (bounds): alpha_i / beta_i = min / max of f over the
- * clamp-to-edge window [-rho, rho]^2 (Algorithm 1, line 2; Prop. 1). Exact
+ * clamp-to-edge window [-rho, rho]^2 (eq. bounds; Prop. 1). Exact
  * (bit-identical to any correct evaluation). alpha/beta: device float32
  * planes with row pitch out_pitch. workspace: >= abf_scratch_bytes(h,w,rho)
  * bytes, 256-byte aligned. rho in [0, ABF_RHO_MAX].
@@ -107,7 +107,7 @@ abf_status abf_minmax(const float* img, int h, int w, long long pitch, int rho,
                       void* workspace, size_t workspace_bytes, void* stream);
 
 /*
- * abf_moment_stack -- Algorithm 1 lines 2 and 6-9 (Props. 1-3): writes the
+ * abf_moment_stack -- window bounds and moment steps of Algorithm 1 (Props. 1-3): writes the
  * moment stack described above into `stack` (>= abf_stack_bytes, 256-byte
  * aligned). The power images are accumulated in FP64 about a local origin
  * and shifted to [alpha_i, beta_i] per pixel. N in [0, ABF_N_MAX].
@@ -121,7 +121,7 @@ abf_status abf_moment_stack(const float* img, int h, int w, long long pitch,
  * abf_stack_moments -- the second half of abf_moment_stack: given a stack
  * whose planes 0 and 1 already hold alpha_i and beta_i for this image and
  * rho (e.g. written by abf_minmax with out_pitch = abf_stack_pitch(w)),
- * writes the moment planes 2..N+1 (Algorithm 1 lines 6-9, Props. 2-3).
+ * writes the moment planes 2..N+1 (moment steps of Algorithm 1, Props. 2-3).
  * Needs no scratch. Lets a caller time or schedule the two spatial
  * kernels separately; abf_moment_stack = abf_minmax + abf_stack_moments.
  */
@@ -131,7 +131,8 @@ abf_status abf_stack_moments(const float* img, int h, int w, long long pitch,
                              void* stream);
 
 /*
- * abf_range -- Algorithm 1 lines 10-20 from a moment stack: the fit
+ * abf_range -- Algorithm 1's per-pixel steps (eqs. inv, sub, I_0, I_1,
+ * F_forward, BFfinal) from a moment stack: the fit
  * c = A^-1 mu (eq. inv, evaluated through the Legendre moments), t0 and
  * lambda (eq. sub), the integrals I_0..I_{N+1} (eqs. I_0, I_1 and the
  * recursion F_forward; for lambda below a threshold where that recursion
@@ -139,7 +140,7 @@ abf_status abf_stack_moments(const float* img, int h, int w, long long pitch,
  * quadrature), and g^ = alpha + (beta - alpha) T1/T2 (eq. BFfinal).
  * img is read only when theta is NULL. If T2 <= 0 or the ratio is not
  * finite the N = 0 estimate I_1/I_0 is used. Where alpha_i == beta_i the
- * output is f(i) (lines 4-5). out: float32 (MIXED) or float64 (FP64) with
+ * output is f(i) (Algorithm 1's flat-window case). out: float32 (MIXED) or float64 (FP64) with
  * row pitch out_pitch (elements).
  */
 abf_status abf_range(const void* stack, size_t stack_bytes, const float* img,
@@ -148,7 +149,7 @@ abf_status abf_range(const void* stack, size_t stack_bytes, const float* img,
                      void* out, long long out_pitch, void* stream);
 
 /*
- * abf_moments_range -- Algorithm 1 lines 6-20 in one pass per pixel: given
+ * abf_moments_range -- Algorithm 1 from the moments on, in one pass per pixel: given
  * a stack whose planes 0 and 1 hold alpha_i and beta_i (abf_minmax with
  * out_pitch = abf_stack_pitch(w)), forms each pixel's moments (Props. 2-3)
  * and finishes the filter from them in registers (the fit of eq. inv, the

@@ -3,20 +3,20 @@
 ``fast_abf``          value of record. It takes Algorithm 1's steps in order,
                       with every step evaluated so that FP64 rounding stays
                       far below the 1e-6 parity bound:
-    1. alpha_i, beta_i = window min/max (eq. bounds, Algorithm 1 line 2);
-       pixels with alpha_i = beta_i output f(i) (lines 4-5).
+    1. alpha_i, beta_i = window min/max (eq. bounds, Algorithm 1);
+       pixels with alpha_i = beta_i output f(i) (Algorithm 1's flat-window case).
     2. the moments of the stretched histogram H_i (eqs. Lambda_tilde, mhist,
        hist_moments_new), taken directly from the window. Props. 2 and 3
        reach the same mu_k through convolutions and a binomial shift; the
        direct sum is that result without the cancellation of the shift.
        They are kept as shifted-Legendre moments
        a~_k = sum_j omega_j P_k(2 y_j - 1) = sum_r ell_kr mu_r.
-    3. c = A^-1 mu (line 11, eq. inv). Because A^-1 = sum_k (2k+1) ell_k
+    3. c = A^-1 mu (eq. inv). Because A^-1 = sum_k (2k+1) ell_k
        ell_k^T (an exact integer identity, pinned in tests),
        c = sum_k (2k+1) a~_k ell_k.
     4. t0 = (theta - alpha)/(beta - alpha), lambda = (beta-alpha)^2/(2 sigma^2)
-       (eq. sub, lines 12-13).
-    5. T1 = sum_k c_k I_{k+1}, T2 = sum_k c_k I_k (lines 15-19) and
+       (eq. sub).
+    5. T1 = sum_k c_k I_{k+1}, T2 = sum_k c_k I_k (Algorithm 1) and
        g^ = alpha + (beta - alpha) T1/T2 (eq. BFfinal). With c from step 3
        these sums equal sum_k (2k+1) a~_k Jt_k and sum_k (2k+1) a~_k J_k,
        where J_k, Jt_k are the Legendre-basis combinations of the I_k,
@@ -30,7 +30,7 @@
 
 ``fast_abf_literal``  the same algorithm exactly as printed, in FP64: f
                       rescaled to [0,1] (Sec. III), gamma_k = omega * f^k by
-                      convolution (line 6, Prop. 2), the binomial shift of
+                      convolution (Prop. 2), the binomial shift of
                       Prop. 3, c = A^-1 mu with the integer A^-1 of eq. (inv),
                       I_0, I_1 and the forward recursion (eqs. I_0, I_1,
                       F_forward). It shows the precision the paper's own
@@ -134,11 +134,11 @@ def fast_abf_literal(f, theta=None, sigma=None, kernel: str = "box", R: int = 3,
     th = f if theta is None else canon(np.asarray(theta, dtype=np.float32)).astype(np.float64)
     sg = np.broadcast_to(np.asarray(sigma, dtype=np.float64), f.shape)
     u, tu, su = f / 255.0, th / 255.0, sg / 255.0                  # Sec. III rescale
-    alpha, beta = window_minmax(u, R)                               # line 2
-    Ainv = np.array(hilbert_inverse(N), dtype=np.float64)          # line 3
-    gam = convolve_powers(u, kernel, R, sigma_s, N)                 # line 6
-    live = alpha != beta                                            # line 4
-    out = f.copy()                                                  # line 5
+    alpha, beta = window_minmax(u, R)                               # eq. bounds
+    Ainv = np.array(hilbert_inverse(N), dtype=np.float64)          # eq. inv
+    gam = convolve_powers(u, kernel, R, sigma_s, N)                 # Prop. 2
+    live = alpha != beta                                            # flat windows
+    out = f.copy()                                                  # keep f(i) there
     a, b = alpha[live], beta[live]
     d = b - a
     m = [g[live] for g in gam]
@@ -148,10 +148,10 @@ def fast_abf_literal(f, theta=None, sigma=None, kernel: str = "box", R: int = 3,
         for r in range(k + 1):
             acc += comb(k, r) * (-a) ** (k - r) * m[r]
         mu[k] = acc / d ** k
-    c = Ainv @ mu                                                   # line 11
-    t0 = (tu[live] - a) / d                                         # line 12
-    lam = 0.5 * d * d / (su[live] ** 2)                            # line 13
-    I = I_paper(lam, t0, N + 1)                                     # lines 14, 17
+    c = Ainv @ mu                                                   # eq. inv
+    t0 = (tu[live] - a) / d                                         # eq. sub
+    lam = 0.5 * d * d / (su[live] ** 2)                            # eq. sub
+    I = I_paper(lam, t0, N + 1)                                     # eqs. I_0, I_1, F_forward
     T1 = np.sum(c.T * I[:, 1:], axis=1)
     T2 = np.sum(c.T * I[:, :-1], axis=1)
     out[live] = 255.0 * (a + d * T1 / T2)

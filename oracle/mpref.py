@@ -1,15 +1,15 @@
 """Algorithm 1 exactly as printed, in 60-digit mpmath arithmetic, for tiny
 images (pins the FP64 routes of ``fast``). Steps, in the paper's order:
 
-  line 2     alpha_i, beta_i: window min/max (eq. bounds);
-  line 3     A^-1 from eq. (inv) (exact integers);
-  line 6     gamma_k(i) = sum_j omega(j) f(i-j)^k (Prop. 2, its definition);
-  line 9     mu from m by the binomial shift of Prop. 3;
-  line 11    c = A^-1 mu;
-  lines 12-13  t0, lambda (eq. sub);
-  line 14    I_0 by eq. (I_0) (two erf), I_1 by eq. (I_1);
-  line 17    I_2..I_{N+1} by eq. (F_forward);
-  lines 15-20  T1, T2 and g^ = alpha + (beta - alpha) T1/T2 (eq. BFfinal).
+  1. alpha_i, beta_i: window min/max (eq. bounds);
+  2. A^-1 from eq. (inv) (exact integers);
+  3. gamma_k(i) = sum_j omega(j) f(i-j)^k (Prop. 2, its definition);
+  4. mu from m by the binomial shift of Prop. 3;
+  5. c = A^-1 mu;
+  6. t0, lambda (eq. sub);
+  7. I_0 by eq. (I_0) (two erf), I_1 by eq. (I_1);
+  8. I_2..I_{N+1} by eq. (F_forward);
+  9. T1, T2 and g^ = alpha + (beta - alpha) T1/T2 (eq. BFfinal).
 
 Clamp-to-edge windows and normalised weights as in ``spatial``. With 60
 digits the forward recursion's loss (at most a factor of about

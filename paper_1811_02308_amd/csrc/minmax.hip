@@ -1,4 +1,4 @@
-// Window bounds alpha_i, beta_i (eq. bounds; Algorithm 1, line 2; Prop. 1).
+// Window bounds alpha_i, beta_i (eq. bounds; Prop. 1; first step of Algorithm 1).
 //
 // The min (max) over the (2R+1)^2 clamp-to-edge window is separable: a
 // 1-D sliding min along rows followed by a 1-D sliding min along columns.

@@ -1,4 +1,4 @@
-// Moment stack: Algorithm 1 lines 6-9 (Props. 2 and 3), fused with the
+// Moment stack: the moment steps of Algorithm 1 (Props. 2 and 3), fused with the
 // change of basis to shifted-Legendre moments.
 //
 // For every pixel i the kernels form the window moments of the power images

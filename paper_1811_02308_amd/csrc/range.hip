@@ -1,4 +1,5 @@
-// Range stage: Algorithm 1 lines 10-20 from the moment stack, one thread
+// Range stage: the per-pixel steps of Algorithm 1 (eqs. inv, sub,
+// I_0, I_1, F_forward, BFfinal) from the moment stack, one thread
 // per pixel, all arithmetic in FP64 registers.
 //
 //   p(t) = sum_k c_k t^k is the degree-N polynomial whose moments on [0,1]

@@ -1,5 +1,6 @@
 // Per-pixel range stage shared by the range kernel and the fused
-// moments-and-range kernels: Algorithm 1 lines 10-20 for one pixel whose
+// moments-and-range kernels: Algorithm 1's per-pixel steps (eqs. inv, sub,
+// I_0, I_1, F_forward, BFfinal) for one pixel whose
 // bounds alpha != beta and Legendre coefficients are known (see range.hip for
 // the method and the choice between the paper's recursion and quadrature).
 #pragma once
