@@ -3,9 +3,16 @@
 
 A step is one pass of the whole fast filter (window bounds, moment stack,
 range stage) over one synthetic image already resident in HBM, issued as
-the three C-ABI calls abf_minmax -> abf_stack_moments -> abf_range on one
-stream (exactly what abf_fast does), with HIP events between them so each
-kernel is timed live. The mixed-precision path is the headline value; the
+the C-ABI calls abf_moment_stack -> abf_range on one stream (exactly what
+abf_fast does). The K timed steps run with no events between the kernels;
+the same K steps are then run again with HIP events around every kernel on
+the launch stream, which gives each kernel's live duration (roofline) and
+the per-step device latency (p50/p99).
+Where the stack takes two kernels (abf_stack_single_pass() == 0: box and
+matrix-core moment kernels) they are issued as abf_minmax ->
+abf_stack_moments, the same two launches, so each is timed on its own; for
+the Gaussian tile kernel the stack is one launch that also takes the window
+bounds. The mixed-precision path is the headline value; the
 all-FP64 path, the fused variant (abf_minmax -> abf_moments_range, moments
 and range stage in one kernel, no moment planes in HBM) and the GPU brute
 force are timed beside it, and parity against the CPU oracle is checked on
@@ -53,6 +60,8 @@ def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
     return {
         "minmax": dict(bytes=px * (4 + 8), flops=0),
         "moments": dict(bytes=px * (4 + 8 + N * b), flops=px * (conv_flops + shift_flops)),
+        # window bounds and moments in one kernel: f in; alpha, beta, a~ out
+        "stack": dict(bytes=px * (4 + 8 + N * b), flops=px * (conv_flops + shift_flops)),
         "range": dict(bytes=px * (8 + N * b + tb + 4 + b), flops=px * range_flops),
         # fused: f, alpha, beta, theta, sigma in; g^ out (the stack never leaves the CU)
         "moments_range": dict(bytes=px * (4 + 8 + tb + 4 + b),
@@ -65,6 +74,7 @@ def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
 STAGE_SOURCES = {
     "minmax": ("minmax.hip", "abf_internal.h"),
     "moments": ("moments.hip", "range_eval.h", "abf_internal.h"),
+    "stack": ("moments.hip", "range_eval.h", "abf_internal.h"),
     "range": ("range.hip", "range_eval.h", "abf_internal.h"),
 }
 
@@ -102,8 +112,8 @@ def measured_traffic(workload: str, stage: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -154,24 +164,34 @@ def main():
     fd, td, sd = dev(f), dev(th), dev(sg)
     scratch = torch.empty(abf.lib().abf_scratch_bytes(H, W, R), dtype=torch.uint8, device="cuda")
 
+    single = abf.stack_single_pass(H, W, kernel, R, N)
+
     def make_path(prec, fused):
         stack = torch.empty(abf.stack_bytes(H, W, N, prec), dtype=torch.uint8, device="cuda")
         out = torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64, device="cuda")
-        names = ["minmax", "moments_range"] if fused else ["minmax", "moments", "range"]
+        if fused:
+            names = ["minmax", "moments_range"]
+        else:
+            names = ["stack", "range"] if single else ["minmax", "moments", "range"]
 
         def step(ev=None):
             if ev is not None:
                 ev[0].record()
-            abf.minmax_into_stack(fd, stack, R, N, prec, workspace=scratch)
-            if ev is not None:
-                ev[1].record()
+            if fused or not single:
+                abf.minmax_into_stack(fd, stack, R, N, prec, workspace=scratch)
+                if ev is not None:
+                    ev[1].record()
             if fused:
                 abf.moments_range(fd, stack, sd, theta=td, kernel=kernel, rho=R, N=N, sigma_s=ss,
                                   precision=prec, out=out)
             else:
-                abf.stack_moments(fd, stack, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec)
+                if single:
+                    abf.moment_stack(fd, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec,
+                                     stack=stack, workspace=scratch)
+                else:
+                    abf.stack_moments(fd, stack, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec)
                 if ev is not None:
-                    ev[2].record()
+                    ev[len(names) - 1].record()
                 abf.range_from_stack(stack, sd, img=fd, theta=td, N=N, precision=prec, out=out)
             if ev is not None:
                 ev[len(names)].record()
@@ -185,12 +205,19 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        # K steps issued back to back on one stream, synchronised on both sides
+        # timed region: K steps issued back to back on one stream, synchronised
+        # on both sides, with no events between the kernels (an event record
+        # costs several microseconds of device time per kernel boundary)
         t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        # the same K steps again with HIP events around every kernel on the
+        # launch stream: per-kernel durations and per-step device latency
         for i in range(steps):
             step(evs[i])
         torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) * 1e3 / steps
         stage_ms = {nm: [e[j].elapsed_time(e[j + 1]) for e in evs] for j, nm in enumerate(names)}
         total_ms = [e[0].elapsed_time(e[-1]) for e in evs]
         return out, stage_ms, total_ms, wall

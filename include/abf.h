@@ -111,6 +111,10 @@ abf_status abf_minmax(const float* img, int h, int w, long long pitch, int rho,
  * moment stack described above into `stack` (>= abf_stack_bytes, 256-byte
  * aligned). The power images are accumulated in FP64 about a local origin
  * and shifted to [alpha_i, beta_i] per pixel. N in [0, ABF_N_MAX].
+ * Where abf_stack_single_pass() is 1 the bounds are taken inside the moment
+ * kernel (one launch, workspace unused); otherwise abf_minmax runs first.
+ * The stack is the same either way, and equals abf_minmax followed by
+ * abf_stack_moments bit for bit. abf_fast builds its stack this way too.
  */
 abf_status abf_moment_stack(const float* img, int h, int w, long long pitch,
                             int kernel_kind, double sigma_s, int rho, int N,
@@ -118,12 +122,22 @@ abf_status abf_moment_stack(const float* img, int h, int w, long long pitch,
                             void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * abf_stack_single_pass -- 1 if abf_moment_stack (and abf_fast) build the
+ * stack of an h x w image with this kernel, rho and N in a single kernel
+ * launch (the Gaussian tile kernel computes the window bounds of eq. bounds
+ * itself), 0 if they launch the bounds kernel and then the moment kernel
+ * (and for invalid arguments). Lets a caller time or plan the launches.
+ */
+int abf_stack_single_pass(int h, int w, int kernel_kind, int rho, int N);
+
+/*
  * abf_stack_moments -- the second half of abf_moment_stack: given a stack
  * whose planes 0 and 1 already hold alpha_i and beta_i for this image and
  * rho (e.g. written by abf_minmax with out_pitch = abf_stack_pitch(w)),
  * writes the moment planes 2..N+1 (moment steps of Algorithm 1, Props. 2-3).
  * Needs no scratch. Lets a caller time or schedule the two spatial
- * kernels separately; abf_moment_stack = abf_minmax + abf_stack_moments.
+ * kernels separately; abf_minmax + abf_stack_moments gives the stack of
+ * abf_moment_stack.
  */
 abf_status abf_stack_moments(const float* img, int h, int w, long long pitch,
                              int kernel_kind, double sigma_s, int rho, int N,

@@ -74,6 +74,7 @@ def lib():
         "abf_workspace_bytes": ([i, i, i, i, i], sz),
         "abf_minmax": ([vp, i, i, ll, i, vp, vp, ll, vp, sz, vp], i),
         "abf_moment_stack": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp, sz, vp], i),
+        "abf_stack_single_pass": ([i, i, i, i, i], i),
         "abf_stack_moments": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp], i),
         "abf_range": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
         "abf_moments_range": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, sz, vp, ll, vp], i),
@@ -230,6 +231,12 @@ def moment_stack(img, kernel="box", rho=3, N=5, sigma_s=0.0, precision="mixed", 
                                 workspace.numel(), _stream(stream))
     _check(st, "abf_moment_stack")
     return stack
+
+
+def stack_single_pass(h, w, kernel="box", rho=3, N=5):
+    """abf_stack_single_pass: True if moment_stack / fast build the stack of
+    an h x w image in one kernel launch (bounds taken by the moment kernel)."""
+    return bool(lib().abf_stack_single_pass(int(h), int(w), _kind(kernel), int(rho), int(N)))
 
 
 def minmax_into_stack(img, stack, rho, N, precision="mixed", workspace=None, stream=None):

@@ -94,17 +94,23 @@ struct FuseSpec {
   int keep_stack = 0;
 };
 
-// prec: 0 = FP64 stack, 1 = FP32 stack. N >= 1. The alpha/beta planes of the
-// stack must already hold the window bounds. fuse != nullptr also evaluates
-// the range stage per pixel and writes the filtered output (only where
-// moments_fusable() holds); the result equals launch_range() on the stack.
+// prec: 0 = FP64 stack, 1 = FP32 stack. N >= 1. Unless `bounds`, the
+// alpha/beta planes of the stack must already hold the window bounds.
+// fuse != nullptr also evaluates the range stage per pixel and writes the
+// filtered output (only where moments_fusable() holds); the result equals
+// launch_range() on the stack. bounds = true (only where
+// moments_take_bounds() holds, without fuse) computes the window bounds in
+// the same kernel and writes them to alpha/beta; the stack is then
+// identical to launch_minmax() followed by launch_moments().
 hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           int kernel_kind, double sigma_s, int rho, int N, int prec,
-                          const float* alpha, const float* beta, long long sp,
+                          float* alpha, float* beta, long long sp,
                           void* mom, long long plane_elems, hipStream_t stream,
-                          const Batch& b = Batch(), const FuseSpec* fuse = nullptr);
+                          const Batch& b = Batch(), const FuseSpec* fuse = nullptr,
+                          bool bounds = false);
 
-bool moments_fusable(int kernel_kind, int rho, int N);
+bool moments_fusable(int kernel_kind, int rho, int N, long long h, long long w);
+bool moments_take_bounds(int kernel_kind, int rho, int N, long long h, long long w);
 
 hipError_t launch_range(const float* alpha, const float* beta, long long sp,
                         const void* mom, long long plane_elems,

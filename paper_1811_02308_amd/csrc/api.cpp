@@ -114,6 +114,44 @@ size_t abf_workspace_bytes(int h, int w, int rho, int N, int precision) {
   return abf_stack_bytes(h, w, N, precision) + abf_scratch_bytes(h, w, rho);
 }
 
+// Window bounds and moment planes of one stack or of a strided batch of
+// stacks (arguments checked by the caller): one launch where the moment
+// kernel takes the bounds as well, else the bounds kernel and then the
+// moment kernel; N = 0 writes the bounds only. The stack is the same either
+// way.
+static hipError_t bounds_and_moments(const float* img, int h, int w, long long pitch,
+                                     int kernel_kind, double sigma_s, int rho, int N,
+                                     int precision, char* stack, void* scratch, hipStream_t s,
+                                     const abf::Batch& b) {
+  const long long sp = abf_stack_pitch(w);
+  float* alpha = reinterpret_cast<float*>(stack);
+  float* beta = reinterpret_cast<float*>(stack + abf_stack_plane_offset(h, w, N, precision, 1));
+  void* mom = stack + abf_stack_plane_offset(h, w, N, precision, 2);
+  const int pc = precision == ABF_PREC_FP64 ? 0 : 1;
+  if (N > 0 && abf::moments_take_bounds(kernel_kind, rho, N, h, w))
+    return abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, pc, alpha, beta,
+                               sp, mom, sp * h, s, b, nullptr, true);
+  hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, scratch, s, b);
+  if (e != hipSuccess || N == 0) return e;
+  return abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, pc, alpha, beta, sp,
+                             mom, sp * h, s, b);
+}
+
+// Range stage of one stack or a strided batch of stacks.
+static abf_status range_batch(const float* img, const float* theta, const float* sigma, int h,
+                              int w, long long pitch, int N, int precision, unsigned flags,
+                              const char* stack, void* out, long long out_pitch, hipStream_t s,
+                              const abf::Batch& b) {
+  const long long sp = abf_stack_pitch(w);
+  const float* alpha = reinterpret_cast<const float*>(stack);
+  const float* beta =
+      reinterpret_cast<const float*>(stack + abf_stack_plane_offset(h, w, N, precision, 1));
+  const void* mom = stack + abf_stack_plane_offset(h, w, N, precision, 2);
+  return hip_status(abf::launch_range(alpha, beta, sp, mom, sp * h, theta ? theta : img, pitch,
+                                      sigma, pitch, h, w, N, precision == ABF_PREC_FP64 ? 0 : 1,
+                                      flags & ABF_FLAG_CLAMP, out, out_pitch, s, b));
+}
+
 abf_status abf_minmax(const float* img, int h, int w, long long pitch, int rho, float* alpha,
                       float* beta, long long out_pitch, void* workspace, size_t workspace_bytes,
                       void* stream) {
@@ -137,8 +175,8 @@ abf_status abf_stack_moments(const float* img, int h, int w, long long pitch, in
   if (N == 0) return ABF_OK;
   const long long sp = abf_stack_pitch(w);
   char* base = static_cast<char*>(stack);
-  const float* alpha = reinterpret_cast<const float*>(base);
-  const float* beta = reinterpret_cast<const float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
+  float* alpha = reinterpret_cast<float*>(base);
+  float* beta = reinterpret_cast<float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
   void* mom = base + abf_stack_plane_offset(h, w, N, precision, 2);
   return hip_status(abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N,
                                         precision == ABF_PREC_FP64 ? 0 : 1, alpha, beta, sp, mom,
@@ -156,15 +194,16 @@ abf_status abf_moment_stack(const float* img, int h, int w, long long pitch, int
   if (!aligned(stack) || stack_bytes < abf_stack_bytes(h, w, N, precision)) return ABF_E_WORKSPACE;
   if (!workspace || !aligned(workspace) || workspace_bytes < abf_scratch_bytes(h, w, rho))
     return ABF_E_WORKSPACE;
-  const long long sp = abf_stack_pitch(w);
-  char* base = static_cast<char*>(stack);
-  float* alpha = reinterpret_cast<float*>(base);
-  float* beta = reinterpret_cast<float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
-  abf_status st = abf_minmax(img, h, w, pitch, rho, alpha, beta, sp, workspace, workspace_bytes,
-                             stream);
-  if (st != ABF_OK) return st;
-  return abf_stack_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N, precision, stack,
-                           stack_bytes, stream);
+  return hip_status(bounds_and_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N, precision,
+                                       static_cast<char*>(stack), workspace,
+                                       static_cast<hipStream_t>(stream), abf::Batch()));
+}
+
+int abf_stack_single_pass(int h, int w, int kernel_kind, int rho, int N) {
+  if (h < 1 || w < 1 || rho < 0 || rho > ABF_RHO_MAX || N < 1 || N > ABF_N_MAX ||
+      !kind_ok(kernel_kind))
+    return 0;
+  return abf::moments_take_bounds(kernel_kind, rho, N, h, w) ? 1 : 0;
 }
 
 abf_status abf_range(const void* stack, size_t stack_bytes, const float* img, const float* theta,
@@ -195,14 +234,13 @@ static abf_status moments_range_batch(const float* img, const float* theta, cons
                                       unsigned flags, char* stack, void* out, long long out_pitch,
                                       hipStream_t s, const abf::Batch& b, bool fused) {
   const long long sp = abf_stack_pitch(w);
-  const float* alpha = reinterpret_cast<const float*>(stack);
-  const float* beta =
-      reinterpret_cast<const float*>(stack + abf_stack_plane_offset(h, w, N, precision, 1));
+  float* alpha = reinterpret_cast<float*>(stack);
+  float* beta = reinterpret_cast<float*>(stack + abf_stack_plane_offset(h, w, N, precision, 1));
   void* mom = stack + abf_stack_plane_offset(h, w, N, precision, 2);
   const int pc = precision == ABF_PREC_FP64 ? 0 : 1;
   const float* th = theta ? theta : img;
   const unsigned rflags = flags & ABF_FLAG_CLAMP;
-  if (fused && N > 0 && abf::moments_fusable(kernel_kind, rho, N)) {
+  if (fused && N > 0 && abf::moments_fusable(kernel_kind, rho, N, h, w)) {
     abf::FuseSpec fs;
     fs.theta = th;
     fs.sigma = sigma;
@@ -250,14 +288,12 @@ abf_status abf_fast(const float* img, const float* theta, const float* sigma, in
     return ABF_E_WORKSPACE;
   const size_t sb = abf_stack_bytes(h, w, N, precision);
   char* ws = static_cast<char*>(workspace);
-  const long long sp = abf_stack_pitch(w);
-  float* alpha = reinterpret_cast<float*>(ws);
-  float* beta = reinterpret_cast<float*>(ws + abf_stack_plane_offset(h, w, N, precision, 1));
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  const hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, ws + sb, s);
+  const hipError_t e = bounds_and_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N,
+                                          precision, ws, ws + sb, s, abf::Batch());
   if (e != hipSuccess) return ABF_E_HIP;
-  return moments_range_batch(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N,
-                             precision, flags, ws, out, out_pitch, s, abf::Batch(), false);
+  return range_batch(img, theta, sigma, h, w, pitch, N, precision, flags, ws, out, out_pitch, s,
+                     abf::Batch());
 }
 
 abf_status abf_range_uniform(const void* stack, size_t stack_bytes, const float* img,
@@ -376,12 +412,11 @@ abf_status abf_fast_strided(const float* img, const float* theta, const float* s
   b.img = n > 1 ? image_stride : 0;
   b.stack = n > 1 ? (long long)sb : 0;
   b.out = n > 1 ? out_image_stride : 0;
-  float* alpha = reinterpret_cast<float*>(base);
-  float* beta = reinterpret_cast<float*>(base + abf_stack_plane_offset(h, w, N, precision, 1));
-  const hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, scratch, s, b);
+  const hipError_t e = bounds_and_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N,
+                                          precision, base, scratch, s, b);
   if (e != hipSuccess) return ABF_E_HIP;
-  return moments_range_batch(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N,
-                             precision, flags, base, out, out_pitch, s, b, false);
+  return range_batch(img, theta, sigma, h, w, pitch, N, precision, flags, base, out, out_pitch, s,
+                     b);
 }
 
 // shared checks of the strided map entry points

@@ -561,23 +561,49 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
 // Phase 1 (vertical): thread t owns padded column t, reads its kTY + 2R
 // inputs once (coalesced across threads), forms the powers once per input
 // and accumulates the kTY x N vertical weighted sums in registers; the sums
-// go to LDS. Phase 2 (horizontal): a thread owns kCB adjacent output columns
-// of one row and accumulates their kCB x N horizontal weighted sums from the
-// (kCB + 2R) LDS columns they span. Phase 3: shift and Legendre basis per
-// pixel (same epilogue as the box kernel, with the exact recompute for
-// ill-conditioned pixels). Work per pixel is O(R), as for the paper's
-// direct convolution.
+// go to LDS. With BOUNDS the same pass takes the column's min/max over each
+// output row's 2R + 1 inputs (the rows' windows share the inputs
+// kTY - 1 .. 2R). Phase 2 (horizontal): a thread owns kCB adjacent output
+// columns of one row and accumulates their kCB x N horizontal weighted sums
+// (with BOUNDS also the min/max, the two windows sharing 2R columns) from
+// the (kCB + 2R) LDS columns they span. Phase 3: shift and Legendre basis
+// per pixel (same epilogue as the box kernel, with the exact recompute for
+// ill-conditioned pixels); with BOUNDS the window bounds alpha_i, beta_i
+// (eq. bounds) are stored as well, so no separate bounds pass is needed.
+// The power sums are taken about the tile's central input value, which the
+// kernel knows before it reads anything else; the stack therefore does not
+// depend on whether the bounds were computed here or read. Work per pixel
+// is O(R), as for the paper's direct convolution.
 constexpr int kTY = 4;   // output rows per tile
 constexpr int kCB = 2;   // adjacent output columns per thread in the horizontal phase
 constexpr int kPF = 8;   // input rows per prefetch chunk in the vertical phase
 
-template <int N, typename TS, bool FUSED>
+// doubles of LDS for the zero-padded tap weights (taps -(kTY-1) .. 2R+kTY-1),
+// rounded up to an even count so that what follows stays 16-byte aligned
+__host__ __device__ constexpr int tile_wext_len(int R) { return 2 * R + 2 * kTY; }
+// widest tile (kTY * kTXMax / kCB <= 256 phase-2 threads) and the narrow LDS
+// row stride, used while TX + 2R fits in it (else 256)
+constexpr int kTXMax = 128;
+constexpr int kESNarrow = 160;
+
+// ES: the LDS row stride (>= TX + 2R), a compile-time constant so that the
+// offsets of the N power planes fold into the LDS instructions' immediates.
+// alpha, beta: read when !BOUNDS, written when BOUNDS.
+template <int N, typename TS, bool FUSED, int ES, bool BOUNDS>
 __global__ __launch_bounds__(256) void moments_gauss_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R, int TX, double inv2s2,
-    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    float* __restrict__ alpha, float* __restrict__ beta, long long sp,
     TS* __restrict__ mom, long long plane, double cond_max, Batch bt, FuseArgs fz) {
-  // [N][kTY][E]; 16-byte aligned for the pair reads of phase 2
+  // (the fused range stage is used with bounds from the stack: with the
+  // bounds taken here as well the kernel was measured slower than the two
+  // kernels of the stack path)
+  static_assert(!(FUSED && BOUNDS), "the fused range stage reads the bounds from the stack");
+  // dynamic LDS: [N][kTY][ES] doubles (vertical sums), the tap weights
+  // (tile_wext_len(R) doubles), then (BOUNDS) [kTY][ES] float2 (min, max);
+  // 16-byte aligned for the pair reads of phase 2
   extern __shared__ __attribute__((aligned(16))) double vsum[];
+  double* const wext = vsum + N * kTY * ES;
+  float2* const vmm = reinterpret_cast<float2*>(wext + tile_wext_len(R));
   img += blockIdx.z * bt.img;
   if (FUSED) {
     fz.theta += blockIdx.z * bt.img;
@@ -587,10 +613,9 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   alpha = byte_offset(alpha, blockIdx.z * bt.stack);
   beta = byte_offset(beta, blockIdx.z * bt.stack);
   mom = byte_offset(mom, blockIdx.z * bt.stack);
-  // 1-D weights of taps -(kTY-1) .. 2R+kTY-1 (zero outside [0, 2R]), so
-  // the phases below apply every tap without a range test; wts = the taps
-  // 0 .. 2R
-  __shared__ double wext[2 * kRhoMax + 2 * kTY];
+  // wext: 1-D weights of taps -(kTY-1) .. 2R+kTY-1 (zero outside [0, 2R]),
+  // so the phases below apply every tap without a range test; wts = the
+  // taps 0 .. 2R
   __shared__ double origin, inv_z;
   double* const wts = wext + (kTY - 1);
   const int E = TX + 2 * R;
@@ -603,8 +628,6 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
     wext[i] = (tap >= 0 && tap <= 2 * R) ? exp(-d * d * inv2s2) : 0.0;
   }
   if (t < kWave) {
-    const int y1 = min(H, y0 + kTY);
-    const double c = wave_origin(alpha, beta, sp, y0, y1, x0, min(TX, W - x0), W, lane);
     // 1-D normalisation: the taps' sum, lane l adding taps l, l + 64, ...
     double zp = 0.0;
     for (int i = lane; i <= 2 * R; i += kWave) {
@@ -614,7 +637,8 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) zp += __shfl_xor(zp, off, kWave);
     if (t == 0) {
-      origin = c;
+      const int yc = min(y0 + kTY / 2, H - 1), xc = min(x0 + TX / 2, W - 1);
+      origin = (double)img[(long long)yc * pitch + xc];
       inv_z = 1.0 / zp;
     }
   }
@@ -640,6 +664,14 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
     for (int r = 0; r < kTY; ++r)
 #pragma unroll
       for (int k = 0; k < N; ++k) acc[r][k] = 0.0;
+    // BOUNDS: min/max of the inputs shared by every row's window (cmn, cmx)
+    // and of each row's other inputs (mn, mx)
+    float cmn = INFINITY, cmx = -INFINITY, mn[kTY], mx[kTY];
+#pragma unroll
+    for (int r = 0; r < kTY; ++r) {
+      mn[r] = INFINITY;
+      mx[r] = -INFINITY;
+    }
     float qn[kPF];
     load_chunk(0, qn);
     for (int i0 = 0; i0 < n_in; i0 += kPF) {
@@ -663,47 +695,102 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
 #pragma unroll
             for (int k = 0; k < N; ++k) acc[r][k] = fma(wv, pw[k], acc[r][k]);
           }
+          if (BOUNDS) {
+            const float v = q[p] + 0.0f;     // -0 -> +0, as the bounds kernel
+            if (i >= kTY - 1 && i <= 2 * R) {
+              cmn = fminf(cmn, v);
+              cmx = fmaxf(cmx, v);
+            } else {
+#pragma unroll
+              for (int r = 0; r < kTY; ++r)
+                if (i >= r && i <= r + 2 * R) {
+                  mn[r] = fminf(mn[r], v);
+                  mx[r] = fmaxf(mx[r], v);
+                }
+            }
+          }
         }
       }
     }
 #pragma unroll
     for (int r = 0; r < kTY; ++r)
 #pragma unroll
-      for (int k = 0; k < N; ++k) vsum[(k * kTY + r) * E + t] = acc[r][k];
+      for (int k = 0; k < N; ++k) vsum[(k * kTY + r) * ES + t] = acc[r][k];
+    if (BOUNDS) {
+#pragma unroll
+      for (int r = 0; r < kTY; ++r)
+        vmm[r * ES + t] = make_float2(fminf(mn[r], cmn), fmaxf(mx[r], cmx));
+    }
   }
   __syncthreads();
 
-  // phase 2: horizontal sums for kCB = 2 adjacent outputs of one row. The
-  // (2 + 2R) LDS columns a thread spans are read as 16-byte pairs: the
+  // phase 2: horizontal sums for kCB adjacent outputs of one row. The
+  // (kCB + 2R) LDS columns a thread spans are read as 16-byte pairs: the
   // pairs of neighbouring lanes are contiguous, so the reads are free of
-  // bank conflicts (E, 2R and the thread's first column are even).
+  // bank conflicts (ES, 2R and the thread's first column are even). Column
+  // c (relative to the thread's first) feeds output v at tap c - v.
   const int groups = TX / kCB;
   const int r = t / groups, gq = t - r * groups;
   const bool active = r < kTY;
   const int xl = kCB * gq;
   double m4[kCB][N + 1];
+  // BOUNDS: window min/max of the outputs; columns kCB - 1 .. 2R are in
+  // every output's window (hmn, hmx), the others in some of them
+  float bmn[kCB], bmx[kCB];
+#pragma unroll
+  for (int v = 0; v < kCB; ++v) {
+    bmn[v] = INFINITY;
+    bmx[v] = -INFINITY;
+  }
   if (active) {
 #pragma unroll
     for (int v = 0; v < kCB; ++v)
 #pragma unroll
       for (int k = 0; k <= N; ++k) m4[v][k] = 0.0;
+    float hmn = INFINITY, hmx = -INFINITY;
     const double2* vs2 = reinterpret_cast<const double2*>(vsum);
+    const float4* vm4 = reinterpret_cast<const float4*>(vmm);
+    auto take = [&](int c, float lo, float hi) {
+      if (c >= kCB - 1 && c <= 2 * R) {
+        hmn = fminf(hmn, lo);
+        hmx = fmaxf(hmx, hi);
+      } else {
+#pragma unroll
+        for (int v = 0; v < kCB; ++v)
+          if (c >= v && c <= v + 2 * R) {
+            bmn[v] = fminf(bmn[v], lo);
+            bmx[v] = fmaxf(bmx[v], hi);
+          }
+      }
+    };
     for (int j = 0; j < kCB + 2 * R; j += 2) {
       double2 val[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) val[k] = vs2[((k * kTY + r) * E + xl + j) >> 1];
-      // column xl + j feeds output v = 0 at tap j and v = 1 at tap j - 1;
-      // column xl + j + 1 feeds v = 0 at tap j + 1 and v = 1 at tap j
-      const double w0 = wts[j];
-      const double w1 = wts[j + 1];      // 0 at j = 2R
-      const double wm = wts[j - 1];      // 0 at j = 0
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        m4[0][k + 1] = fma(w0, val[k].x, m4[0][k + 1]);
-        m4[0][k + 1] = fma(w1, val[k].y, m4[0][k + 1]);
-        m4[1][k + 1] = fma(wm, val[k].x, m4[1][k + 1]);
-        m4[1][k + 1] = fma(w0, val[k].y, m4[1][k + 1]);
+      for (int k = 0; k < N; ++k) val[k] = vs2[((k * kTY + r) * ES + xl + j) >> 1];
+      if (BOUNDS) {
+        // (min, max) of columns xl + j and xl + j + 1
+        const float4 q = vm4[(r * ES + xl + j) >> 1];
+        take(j, q.x, q.y);
+        take(j + 1, q.z, q.w);
       }
+      double wa[kCB], wb[kCB];        // taps j - v and j + 1 - v (0 outside [0, 2R])
+#pragma unroll
+      for (int v = 0; v < kCB; ++v) {
+        wa[v] = wts[j - v];
+        wb[v] = wts[j + 1 - v];
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int v = 0; v < kCB; ++v) {
+          m4[v][k + 1] = fma(wa[v], val[k].x, m4[v][k + 1]);
+          m4[v][k + 1] = fma(wb[v], val[k].y, m4[v][k + 1]);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < kCB; ++v) {
+      bmn[v] = fminf(bmn[v], hmn);
+      bmx[v] = fmaxf(bmx[v], hmx);
     }
   }
   // phase 3: per-pixel epilogue (all lanes take part in the wave ballots)
@@ -720,8 +807,15 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
       m[0] = 1.0;
 #pragma unroll
       for (int k = 1; k <= N; ++k) m[k] = m4[v][k] * norm;
-      a = alpha[idx];
-      b = beta[idx];
+      if (BOUNDS) {
+        a = bmn[v];
+        b = bmx[v];
+        alpha[idx] = a;
+        beta[idx] = b;
+      } else {
+        a = alpha[idx];
+        b = beta[idx];
+      }
       bad = legendre_from_moments<N>(m, a, b, c, cond_max);
       if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
     }
@@ -926,7 +1020,7 @@ int gauss_tile_tx(int R, int N) {
   int e = 65536 / (kTY * 8 * N);          // padded columns within 64 KiB of LDS
   if (e > 256) e = 256;                   // one phase-1 thread per padded column
   int tx = e - 2 * R;
-  if (tx > 128) tx = 128;                 // kTY * tx / kCB <= 256 phase-2 threads
+  if (tx > kTXMax) tx = kTXMax;
   tx &= ~(kCB - 1);
   return tx >= kCB ? tx : 0;
 }
@@ -967,11 +1061,19 @@ int device_cus() {
   return cus;
 }
 
+// The matrix-core kernel is the faster one for wide windows on large
+// images (measured: at 2048^2 and 4096^2 with 8 <= R <= 16 it takes 0.8-0.95
+// of the tile kernel's time; at 1024^2 they tie, below that it is slower).
+bool gauss_on_mfma(int R, long long h, long long w) {
+  return R <= kMfmaRMax && R >= 8 && h * w >= (1LL << 22);
+}
+
 template <int N, typename TS>
 hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int kind,
-                            double sigma_s, int R, const float* alpha, const float* beta,
+                            double sigma_s, int R, float* alpha, float* beta,
                             long long sp, TS* mom, long long plane, hipStream_t stream,
-                            const Batch& b, const FuseSpec* fs) {
+                            const Batch& b, const FuseSpec* fs, bool bounds) {
+  if (bounds && (fs || !moments_take_bounds(kind, R, N, h, w))) return hipErrorNotSupported;
   // resident waves of the box kernel on this device (occupancy x CUs); the
   // segment geometry depends on the image and device only (not on the batch
   // size), so an image gets bit-identical moments alone or in a batch
@@ -1012,10 +1114,7 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     return hipGetLastError();
   }
   const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
-  // the matrix-core kernel is the faster one for wide windows on large
-  // images (measured: at 2048^2 and 4096^2 with 8 <= R <= 16 it takes 0.8-0.95
-  // of the tile kernel's time; at 1024^2 they tie, below that it is slower)
-  if (!fs && R <= kMfmaRMax && R >= 8 && (long long)h * w >= (1LL << 22)) {
+  if (!fs && gauss_on_mfma(R, h, w)) {
     // strips of 16 columns; segment height a multiple of 16, chosen so the
     // grid has about two waves per SIMD (8 per CU)
     const int n_strips = (w + 15) / 16;
@@ -1034,14 +1133,25 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   const int tx = gauss_tile_tx(R, N);
   if (tx > 0) {
     dim3 tg((w + tx - 1) / tx, (h + kTY - 1) / kTY, b.n);
-    const size_t lds = (size_t)N * kTY * (tx + 2 * R) * sizeof(double);
     const double i2 = 1.0 / (2.0 * s * s);
-    if (fs)
-      hipLaunchKernelGGL((moments_gauss_tile<N, TS, true>), tg, dim3(256), lds, stream, img,
-                         pitch, h, w, R, tx, i2, alpha, beta, sp, mom, plane, cond_max, b, fz);
-    else
-      hipLaunchKernelGGL((moments_gauss_tile<N, TS, false>), tg, dim3(256), lds, stream, img,
-                         pitch, h, w, R, tx, i2, alpha, beta, sp, mom, plane, cond_max, b, fz);
+    // LDS row stride: kESNarrow when the padded tile fits, else 256
+    // (tx + 2R <= 256 by the choice of tx)
+    const bool narrow = tx + 2 * R <= kESNarrow;
+    const int es = narrow ? kESNarrow : 256;
+    // power sums, then (bounds) the (min, max) pairs
+    const size_t lds = (size_t)(N * kTY * es + tile_wext_len(R)) * sizeof(double) +
+                       (bounds ? (size_t)(kTY * es) * sizeof(float2) : 0);
+#define ABF_TILE(F, S, B)                                                                       \
+  hipLaunchKernelGGL((moments_gauss_tile<N, TS, F, S, B>), tg, dim3(256), lds, stream, img, pitch, \
+                     h, w, R, tx, i2, alpha, beta, sp, mom, plane, cond_max, b, fz)
+    if (fs) {
+      if (narrow) ABF_TILE(true, kESNarrow, false); else ABF_TILE(true, 256, false);
+    } else if (bounds) {
+      if (narrow) ABF_TILE(false, kESNarrow, true); else ABF_TILE(false, 256, true);
+    } else {
+      if (narrow) ABF_TILE(false, kESNarrow, false); else ABF_TILE(false, 256, false);
+    }
+#undef ABF_TILE
     return hipGetLastError();
   }
   if (fs) return hipErrorNotSupported;   // callers check moments_fusable() first
@@ -1056,12 +1166,12 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
 
 template <typename TS>
 hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, int kind,
-                      double sigma_s, int R, const float* alpha, const float* beta,
+                      double sigma_s, int R, float* alpha, float* beta,
                       long long sp, TS* mom, long long plane, hipStream_t stream,
-                      const Batch& b, const FuseSpec* fs) {
+                      const Batch& b, const FuseSpec* fs, bool bounds) {
   switch (N) {
 #define ABF_CASE(n) \
-  case n: return launch_moments_t<n, TS>(img, pitch, h, w, kind, sigma_s, R, alpha, beta, sp, mom, plane, stream, b, fs);
+  case n: return launch_moments_t<n, TS>(img, pitch, h, w, kind, sigma_s, R, alpha, beta, sp, mom, plane, stream, b, fs, bounds);
     ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6) ABF_CASE(7) ABF_CASE(8)
 #undef ABF_CASE
     default: return hipErrorInvalidValue;
@@ -1072,23 +1182,33 @@ hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, in
 
 hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           int kernel_kind, double sigma_s, int rho, int N, int prec,
-                          const float* alpha, const float* beta, long long sp,
+                          float* alpha, float* beta, long long sp,
                           void* mom, long long plane_elems, hipStream_t stream, const Batch& b,
-                          const FuseSpec* fuse) {
+                          const FuseSpec* fuse, bool bounds) {
   if (prec == 0)
     return dispatch_n<double>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
-                              static_cast<double*>(mom), plane_elems, stream, b, fuse);
+                              static_cast<double*>(mom), plane_elems, stream, b, fuse, bounds);
   return dispatch_n<float>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
-                           static_cast<float*>(mom), plane_elems, stream, b, fuse);
+                           static_cast<float*>(mom), plane_elems, stream, b, fuse, bounds);
 }
 
-bool moments_fusable(int kernel_kind, int rho, int N) {
-  // The fused variant has no matrix-core form; where abf_stack_moments may
-  // use the matrix-core kernel (Gaussian, 8 <= rho <= 16) the fused call
-  // takes the stack path, so that its output stays identical to
-  // abf_stack_moments + abf_range.
-  return N >= 1 &&
-         (kernel_kind == 0 || ((rho < 8 || rho > kMfmaRMax) && gauss_tile_tx(rho, N) > 0));
+bool moments_take_bounds(int kernel_kind, int rho, int N, long long h, long long w) {
+  // the Gaussian tile kernel (its LDS, the power sums and the (min, max)
+  // pairs, (N + 1) kTY ES 8 bytes, plus the weights, is at most 74 KiB, so
+  // two workgroups still share a CU's 160 KiB, as without the pairs); the
+  // box and matrix-core kernels read the bounds from the stack
+  if (kernel_kind != 1 || N < 1 || N > 8 || gauss_on_mfma(rho, h, w)) return false;
+  const int tx = gauss_tile_tx(rho, N);
+  const int es = tx + 2 * rho <= kESNarrow ? kESNarrow : 256;
+  return tx > 0 && ((N + 1) * kTY * es + tile_wext_len(rho)) * 8 + 64 <= 81920;
+}
+
+bool moments_fusable(int kernel_kind, int rho, int N, long long h, long long w) {
+  // The fused variant has no matrix-core form; where abf_stack_moments uses
+  // the matrix-core kernel the fused call takes the stack path, so that its
+  // output stays identical to abf_stack_moments + abf_range.
+  return N >= 1 && N <= 8 &&
+         (kernel_kind == 0 || (!gauss_on_mfma(rho, h, w) && gauss_tile_tx(rho, N) > 0));
 }
 
 }  // namespace abf

@@ -99,3 +99,22 @@ def test_other_entry_points_validate():
     reqs[0] = abf.Request(1, None, 1, 4, 4, 4, 0, 0.0, 1, 12, 1, 4)
     assert L.abf_fast_batched(reqs, 1, 1, 1, None, 0, None) == -4
     assert L.abf_fast_batched(reqs, 0, 1, 1, None, 0, None) == 0
+
+
+def test_stack_single_pass_query():
+    """The bounds are taken inside the Gaussian tile kernel; the box kernel
+    and the matrix-core kernel (8 <= rho <= 16 on images of 4 Mpix or more)
+    read them from a separate bounds pass. No device call is made."""
+    L = abf.lib()
+    assert L.abf_stack_single_pass(1024, 1024, 1, 15, 6) == 1
+    assert L.abf_stack_single_pass(333, 340, 1, 3, 5) == 1
+    assert L.abf_stack_single_pass(1024, 1024, 0, 15, 6) == 0      # box
+    assert L.abf_stack_single_pass(2048, 2048, 1, 15, 6) == 0      # matrix cores
+    assert L.abf_stack_single_pass(2048, 2048, 1, 20, 6) == 1
+    assert L.abf_stack_single_pass(1024, 1024, 1, 40, 7) == 1
+    assert L.abf_stack_single_pass(1024, 1024, 1, 90, 8) == 1
+    assert L.abf_stack_single_pass(1024, 1024, 1, 15, 0) == 0      # no moments
+    assert L.abf_stack_single_pass(0, 1024, 1, 15, 6) == 0
+    assert L.abf_stack_single_pass(16, 16, 1, -1, 6) == 0
+    assert L.abf_stack_single_pass(16, 16, 1, 3, 9) == 0
+    assert L.abf_stack_single_pass(16, 16, 5, 3, 6) == 0

@@ -259,6 +259,40 @@ def test_stack_reuse_for_new_theta_sigma(torch, abf):
         assert torch.equal(a, b)
 
 
+SINGLE_PASS = [((256, 300), 15, 6), ((37, 300), 5, 8), ((300, 37), 20, 5), ((1, 129), 4, 6),
+               ((129, 1), 4, 6), ((5, 7), 20, 3), ((1, 1), 3, 2), ((70, 90), 0, 6), ((70, 90), 1, 7),
+               ((130, 517), 2, 1), ((150, 700), 12, 8), ((120, 400), 40, 7), ((90, 260), 60, 8)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,R,N", SINGLE_PASS)
+def test_single_pass_stack_equals_two_pass(torch, abf, precision, shape, R, N):
+    """Where the Gaussian tile kernel takes the window bounds itself
+    (abf_stack_single_pass), abf_moment_stack equals abf_minmax followed by
+    abf_stack_moments bit for bit, and its bounds are the exact window
+    min/max (with -0 stored as +0). The image has noisy rectangles, a
+    near-flat patch (exact recompute of ill-conditioned shifts) and -0."""
+    h, w = shape
+    f = rect_scene(300 + R + N, h, w, n_rect=6, noise=0.7, side_lo=2, side_hi=60)
+    f[h // 3: h // 3 + 20, w // 4: w // 4 + 40] = np.float32(250.0)
+    f[h // 3: h // 3 + 20, w // 4: w // 4 + 40] += (np.arange(min(40, w - w // 4), dtype=np.float32) % 3) * np.float32(0.25)
+    f[::7, ::5] = np.float32(-0.0)
+    assert abf.stack_single_pass(h, w, "gaussian", R, N)
+    img = dev(torch, f)
+    one = abf.moment_stack(img, kernel="gaussian", rho=R, N=N, precision=precision)
+    two = torch.zeros_like(one)
+    abf.minmax_into_stack(img, two, R, N, precision=precision)
+    abf.stack_moments(img, two, kernel="gaussian", rho=R, N=N, precision=precision)
+    torch.cuda.synchronize()
+    p1 = abf.stack_planes(one, h, w, N, precision)
+    p2 = abf.stack_planes(two, h, w, N, precision)
+    for a, b in zip((p1[0], p1[1], *p1[2]), (p2[0], p2[1], *p2[2])):
+        assert torch.equal(a, b)
+    lo, hi = window_minmax(f, R)
+    assert np.array_equal(p1[0].cpu().numpy().view(np.uint32), lo.astype(np.float32).view(np.uint32))
+    assert np.array_equal(p1[1].cpu().numpy().view(np.uint32), hi.astype(np.float32).view(np.uint32))
+
+
 FUSED_CASES = [("box", 3, 5), ("box", 20, 8), ("box", 5, 1), ("gaussian", 15, 6), ("gaussian", 4, 8),
                ("gaussian", 40, 7)]
 
