@@ -4,10 +4,13 @@
 A step is one pass of the whole fast filter (window bounds, moment stack,
 range stage) over one synthetic image already resident in HBM, issued as
 the C-ABI calls abf_moment_stack -> abf_range on one stream (exactly what
-abf_fast does). The K timed steps run with no events between the kernels;
-the same K steps are then run again with HIP events around every kernel on
-the launch stream, which gives each kernel's live duration (roofline) and
-the per-step device latency (p50/p99).
+abf_fast does). The K timed steps alternate between two streams, each with
+its own stack and output buffers, so two images are in flight (one image's
+kernels fill the other's kernel tails and launch gaps), with no events
+between the kernels. The same K steps then run on one stream (the
+single-stream rate, reported beside the value) and once more on one stream
+with HIP events around every kernel, which gives each kernel's live
+duration (roofline) and the per-step device latency (p50/p99).
 Where the stack takes two kernels (abf_stack_single_pass() == 0: box and
 matrix-core moment kernels) they are issued as abf_minmax ->
 abf_stack_moments, the same two launches, so each is timed on its own; for
@@ -37,6 +40,7 @@ METRIC = "Mpix/s fast-ABF mixed vs all-FP64 on GPU at max err≤0.05/255; p50/p9
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
 DEFAULT_WORKLOAD = "sharpen1024_gauss15_n6"
+N_STREAMS = 2                  # images in flight in the timed steps
 
 
 def log(*a):
@@ -112,8 +116,8 @@ def measured_traffic(workload: str, stage: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -162,75 +166,99 @@ def main():
 
     dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
     fd, td, sd = dev(f), dev(th), dev(sg)
-    scratch = torch.empty(abf.lib().abf_scratch_bytes(H, W, R), dtype=torch.uint8, device="cuda")
 
     single = abf.stack_single_pass(H, W, kernel, R, N)
+    # the timed steps alternate between two streams, each with its own stack,
+    # scratch and output buffers (two images in flight: one image's kernels
+    # fill the other's kernel tails and launch gaps)
+    streams = [torch.cuda.Stream() for _ in range(N_STREAMS)]
 
     def make_path(prec, fused):
-        stack = torch.empty(abf.stack_bytes(H, W, N, prec), dtype=torch.uint8, device="cuda")
-        out = torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64, device="cuda")
+        bufs = []
+        for _ in range(N_STREAMS):
+            bufs.append((torch.empty(abf.stack_bytes(H, W, N, prec), dtype=torch.uint8, device="cuda"),
+                         torch.empty(abf.lib().abf_scratch_bytes(H, W, R), dtype=torch.uint8, device="cuda"),
+                         torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64,
+                                     device="cuda")))
         if fused:
             names = ["minmax", "moments_range"]
         else:
             names = ["stack", "range"] if single else ["minmax", "moments", "range"]
 
-        def step(ev=None):
+        def step(j=0, stream=None, ev=None):
+            stack, scr, out = bufs[j]
             if ev is not None:
                 ev[0].record()
             if fused or not single:
-                abf.minmax_into_stack(fd, stack, R, N, prec, workspace=scratch)
+                abf.minmax_into_stack(fd, stack, R, N, prec, workspace=scr, stream=stream)
                 if ev is not None:
                     ev[1].record()
             if fused:
                 abf.moments_range(fd, stack, sd, theta=td, kernel=kernel, rho=R, N=N, sigma_s=ss,
-                                  precision=prec, out=out)
+                                  precision=prec, out=out, stream=stream)
             else:
                 if single:
                     abf.moment_stack(fd, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec,
-                                     stack=stack, workspace=scratch)
+                                     stack=stack, workspace=scr, stream=stream)
                 else:
-                    abf.stack_moments(fd, stack, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec)
+                    abf.stack_moments(fd, stack, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec,
+                                      stream=stream)
                 if ev is not None:
                     ev[len(names) - 1].record()
-                abf.range_from_stack(stack, sd, img=fd, theta=td, N=N, precision=prec, out=out)
+                abf.range_from_stack(stack, sd, img=fd, theta=td, N=N, precision=prec, out=out,
+                                     stream=stream)
             if ev is not None:
                 ev[len(names)].record()
 
-        return out, step, names
+        return bufs, step, names
 
     def time_path(prec, steps, warmup, fused=False):
-        out, step, names = make_path(prec, fused)
+        bufs, step, names = make_path(prec, fused)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
                for _ in range(steps)]
-        for _ in range(warmup):
-            step()
+        cur = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(cur)
+        for i in range(warmup):
+            step(i % N_STREAMS, streams[i % N_STREAMS])
         torch.cuda.synchronize()
-        # timed region: K steps issued back to back on one stream, synchronised
-        # on both sides, with no events between the kernels (an event record
-        # costs several microseconds of device time per kernel boundary)
+        # timed region: K steps issued back to back, alternating between the
+        # streams, synchronised on both sides, with no events between the
+        # kernels (an event record costs several microseconds of device time
+        # per kernel boundary)
         t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
+        for i in range(steps):
+            step(i % N_STREAMS, streams[i % N_STREAMS])
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / steps
-        # the same K steps again with HIP events around every kernel on the
+        # the same K steps on one stream, no events: the single-stream rate
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall1 = (time.perf_counter() - t0) * 1e3 / steps
+        # and again on one stream with HIP events around every kernel on the
         # launch stream: per-kernel durations and per-step device latency
         for i in range(steps):
-            step(evs[i])
+            step(ev=evs[i])
         torch.cuda.synchronize()
         stage_ms = {nm: [e[j].elapsed_time(e[j + 1]) for e in evs] for j, nm in enumerate(names)}
         total_ms = [e[0].elapsed_time(e[-1]) for e in evs]
-        return out, stage_ms, total_ms, wall
+        outs = [b[2] for b in bufs]
+        for o in outs[1:]:
+            if not torch.equal(o, outs[0]):
+                raise RuntimeError("the streams' outputs differ")
+        return outs[0], stage_ms, total_ms, wall, wall1
 
     # ---------------------------------------------------------- timed region
     log("timing mixed path ...")
-    out_m, st_m, tot_m, wall_m = time_path("mixed", args.steps, args.warmup)
+    out_m, st_m, tot_m, wall_m, wall1_m = time_path("mixed", args.steps, args.warmup)
     log("timing fp64 path ...")
-    out_d, st_d, tot_d, wall_d = time_path("fp64", args.steps, args.warmup)
+    out_d, st_d, tot_d, wall_d, wall1_d = time_path("fp64", args.steps, args.warmup)
     log("timing the fused variant ...")
     fu_steps = max(5, args.steps // 5)
-    out_s, st_s, tot_s, wall_s = time_path("mixed", fu_steps, 2, fused=True)
-    out_sd, st_sd, tot_sd, wall_sd = time_path("fp64", fu_steps, 2, fused=True)
+    out_s, st_s, tot_s, wall_s, _ = time_path("mixed", fu_steps, 2, fused=True)
+    out_sd, st_sd, tot_sd, wall_sd, _ = time_path("fp64", fu_steps, 2, fused=True)
     fused_equal = bool(torch.equal(out_s, out_m) and torch.equal(out_sd, out_d))
 
     med = lambda v: float(np.median(v))
@@ -326,7 +354,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "h": H, "w": W, "kernel": kernel, "rho": R, "N": N,
-                   "sigma_s": ss, "precision": "mixed (FP64 arithmetic, FP32 stack and output)"},
+                   "sigma_s": ss, "precision": "mixed (FP64 arithmetic, FP32 stack and output)",
+                   "streams": N_STREAMS},
+        "single_stream": {"value": round(mpix / (wall1_m * 1e-3), 2), "ms_per_step": round(wall1_m, 5),
+                          "fp64_value": round(mpix / (wall1_d * 1e-3), 2)},
         "latency_ms": {"p50": round(float(np.percentile(lat_m, 50)), 5),
                        "p99": round(float(np.percentile(lat_m, 99)), 5)},
         "stage_ms_mixed": {k: round(v, 5) for k, v in stages.items()},

@@ -616,12 +616,29 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   // wext: 1-D weights of taps -(kTY-1) .. 2R+kTY-1 (zero outside [0, 2R]),
   // so the phases below apply every tap without a range test; wts = the
   // taps 0 .. 2R
-  __shared__ double origin, inv_z;
+  __shared__ double inv_z;
   double* const wts = wext + (kTY - 1);
   const int E = TX + 2 * R;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * kTY;
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1);
+  const int tc = t;                    // phase 1: padded column tc
+  // loads that depend on nothing else go out before the weights are formed:
+  // the tile's central input value (the origin of the power sums; one
+  // cache line for the whole workgroup) and the first rows of the column
+  const int yc = min(y0 + kTY / 2, H - 1), xc = min(x0 + TX / 2, W - 1);
+  const float cval = img[(long long)yc * pitch + xc];
+  const int n_in = kTY + 2 * R;
+  const float* col = img + min(max(x0 - R + tc, 0), W - 1);
+  auto load_chunk = [&](int i0, float (&q)[kPF]) {
+#pragma unroll
+    for (int p = 0; p < kPF; ++p) {
+      const int i = min(i0 + p, n_in - 1);
+      q[p] = col[(long long)min(max(y0 - R + i, 0), H - 1) * pitch];
+    }
+  };
+  float qn[kPF];
+  if (tc < E) load_chunk(0, qn);
   for (int i = t; i < 2 * R + 2 * kTY - 1; i += blockDim.x) {
     const int tap = i - (kTY - 1);
     const double d = (double)(tap - R);
@@ -636,29 +653,16 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) zp += __shfl_xor(zp, off, kWave);
-    if (t == 0) {
-      const int yc = min(y0 + kTY / 2, H - 1), xc = min(x0 + TX / 2, W - 1);
-      origin = (double)img[(long long)yc * pitch + xc];
-      inv_z = 1.0 / zp;
-    }
+    if (t == 0) inv_z = 1.0 / zp;
   }
   __syncthreads();
   const double iz = inv_z;
-  const double c = origin;
+  const double c = (double)cval;
 
-  // phase 1: vertical sums for padded column t. The column's inputs are
+  // phase 1: vertical sums for padded column tc. The column's inputs are
   // read in chunks of kPF rows, the next chunk's loads issued before the
   // current chunk is used, so memory latency overlaps the arithmetic.
-  if (t < E) {
-    const float* col = img + min(max(x0 - R + t, 0), W - 1);
-    const int n_in = kTY + 2 * R;
-    auto load_chunk = [&](int i0, float (&q)[kPF]) {
-#pragma unroll
-      for (int p = 0; p < kPF; ++p) {
-        const int i = min(i0 + p, n_in - 1);
-        q[p] = col[(long long)min(max(y0 - R + i, 0), H - 1) * pitch];
-      }
-    };
+  if (tc < E) {
     double acc[kTY][N];
 #pragma unroll
     for (int r = 0; r < kTY; ++r)
@@ -672,8 +676,6 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
       mn[r] = INFINITY;
       mx[r] = -INFINITY;
     }
-    float qn[kPF];
-    load_chunk(0, qn);
     for (int i0 = 0; i0 < n_in; i0 += kPF) {
       float q[kPF];
 #pragma unroll
@@ -715,11 +717,11 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
 #pragma unroll
     for (int r = 0; r < kTY; ++r)
 #pragma unroll
-      for (int k = 0; k < N; ++k) vsum[(k * kTY + r) * ES + t] = acc[r][k];
+      for (int k = 0; k < N; ++k) vsum[(k * kTY + r) * ES + tc] = acc[r][k];
     if (BOUNDS) {
 #pragma unroll
       for (int r = 0; r < kTY; ++r)
-        vmm[r * ES + t] = make_float2(fminf(mn[r], cmn), fmaxf(mx[r], cmx));
+        vmm[r * ES + tc] = make_float2(fminf(mn[r], cmn), fmaxf(mx[r], cmx));
     }
   }
   __syncthreads();
