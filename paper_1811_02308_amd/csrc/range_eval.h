@@ -6,6 +6,7 @@
 #pragma once
 
 #include "abf_internal.h"
+#include "erfcx_weideman.h"
 
 namespace abf {
 
@@ -75,6 +76,23 @@ __device__ __forceinline__ double rcp(double x) {
   return r;
 }
 
+// erfcx(x) = exp(x^2) erfc(x) for x >= 0 by Weideman's rational expansion
+// of the Faddeeva function on the real axis (SIAM J. Numer. Anal. 31(5),
+// 1994): with r = 1/(L + x) and Z = (L - x)/(L + x) = 2 L r - 1,
+// erfcx(x) = r (2 r p(Z) + 1/sqrt(pi)), p of degree kErfcxTerms - 1
+// (coefficients from gen_erfcx.py). Relative error below 1.3e-15 for
+// finite x >= 0 (checked against 40-digit values), tending to the
+// function's own limit 1/(sqrt(pi) x). About 45 instructions, against
+// about 130 for the library's erfcx (used by the FP64 path).
+__device__ __forceinline__ double erfcx_w(double x) {
+  const double r = rcp(kErfcxL + x);
+  const double z = fma(2.0 * kErfcxL, r, -1.0);
+  double p = kErfcxA[0];
+#pragma unroll
+  for (int n = 1; n < kErfcxTerms; ++n) p = fma(p, z, kErfcxA[n]);
+  return r * fma(2.0 * r, p, 0.56418958354775628695);     // 1/sqrt(pi)
+}
+
 // g^ = a + (b - a) F for one pixel and the interval [a, b] (a < b; the
 // window bounds alpha, beta in Algorithm 1). ak[k] = (2k+1) a~_k with
 // ak[0] = 1; th = theta, sg = sigma at the pixel.
@@ -115,8 +133,11 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
     // with erfc(|z|) = erfcx(|z|) exp(-z^2), the e^s folded into E0 and E1.
     // Two erfcx calls per pixel in every case, so a wave whose lanes fall in
     // different cases does not run several inlined copies one after another.
-    const double X0 = erfcx(fabs(A)) * E0;
-    const double X1 = erfcx(fabs(B)) * E1;
+    // (the mixed path takes the shorter expansion: measured 7% faster there,
+    // with a margin of ~1e3 to the mixed tolerance; the FP64 path keeps the
+    // library function's last ulps)
+    const double X0 = (kMixed ? erfcx_w(fabs(A)) : erfcx(fabs(A))) * E0;
+    const double X1 = (kMixed ? erfcx_w(fabs(B)) : erfcx(fabs(B))) * E1;
     const bool straddle = A <= 0.0 && B >= 0.0;
     const double diff = (straddle ? 2.0 - X1 : (A > 0.0 ? -X1 : X1)) + (A > 0.0 ? X0 : -X0);
     const double i2l = 0.5 * rcp(lam);
