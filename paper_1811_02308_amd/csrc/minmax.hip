@@ -113,11 +113,16 @@ __global__ __launch_bounds__(kThreads) void vh_rows(
 //     per thread, written straight to alpha/beta.
 // No intermediate leaves the workgroup; f is read once (+ halo from L2).
 constexpr int kMTX = 64, kMTY = 32, kTileRMax = 24, kHS = kMTX + 1;
+// horizontal items per thread: (kMTY + 2 kTileRMax) kMTX / 8 <= kHItems kThreads
+constexpr int kHItems = 3;
+static_assert((kMTY + 2 * kTileRMax) * (kMTX / 8) <= kHItems * kThreads, "horizontal items per thread");
 
 template <typename Get>
 __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&mx)[8]) {
-  // windows [v, v + 2R] of the sequence get(0 .. 7 + 2R)
-  if (2 * R < 7) {
+  // windows [v, v + 2R] of the sequence get(0 .. 7 + 2R). For 2R >= 6 each
+  // window is [v, 6] + [7, 2R] (the shared core, empty at 2R = 6) +
+  // [2R + 1, 2R + v]; smaller windows are taken directly.
+  if (2 * R < 6) {
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       float lo = INFINITY, hi = -INFINITY;
@@ -170,11 +175,13 @@ __global__ __launch_bounds__(kThreads) void minmax_tile(
   out_b = byte_offset(out_b, blockIdx.z * bt.stack);
   // LDS row strides: odd for the padded tile and kMTX + 1 for the
   // horizontal result, so that threads walking different rows hit
-  // different banks
+  // different banks. The horizontal result takes the tile's place once the
+  // tile has been read (it is held in registers across a barrier), so the
+  // LDS footprint is the larger of the two, not their sum.
   const int EX = kMTX + 2 * R, EY = kMTY + 2 * R;
   const int XS = EX | 1;
   float* tile = lds;                                       // EY x XS
-  float2* hres = reinterpret_cast<float2*>(lds + ((EY * XS + 1) & ~1));   // EY x kHS
+  float2* hres = reinterpret_cast<float2*>(lds);           // EY x kHS, after the tile
   const int x0 = blockIdx.x * kMTX, y0 = blockIdx.y * kMTY;
   for (int i = threadIdx.x; i < EY * EX; i += kThreads) {
     const int r = i / EX, c = i - r * EX;
@@ -183,14 +190,28 @@ __global__ __launch_bounds__(kThreads) void minmax_tile(
     tile[r * XS + c] = img[(long long)gy * pitch + gx] + 0.0f;
   }
   __syncthreads();
-  // horizontal: item = (padded row, group of 8 outputs); rows vary fastest
-  for (int it = threadIdx.x; it < EY * (kMTX / 8); it += kThreads) {
-    const int r = it % EY, g = it / EY;
-    const float* row = tile + r * XS + 8 * g;
-    float mn[8], mx[8];
-    slide8([&](int i) { const float v = row[i]; return make_float2(v, v); }, R, mn, mx);
+  // horizontal: item = (padded row, group of 8 outputs); rows vary fastest;
+  // EY * kMTX / 8 <= kHItems * kThreads items
+  const int n_items = EY * (kMTX / 8);
+  float hmn[kHItems][8], hmx[kHItems][8];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) hres[r * kHS + 8 * g + v] = make_float2(mn[v], mx[v]);
+  for (int q = 0; q < kHItems; ++q) {
+    const int it = threadIdx.x + q * kThreads;
+    if (it < n_items) {
+      const int r = it % EY, g = it / EY;
+      const float* row = tile + r * XS + 8 * g;
+      slide8([&](int i) { const float v = row[i]; return make_float2(v, v); }, R, hmn[q], hmx[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kHItems; ++q) {
+    const int it = threadIdx.x + q * kThreads;
+    if (it < n_items) {
+      const int r = it % EY, g = it / EY;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) hres[r * kHS + 8 * g + v] = make_float2(hmn[q][v], hmx[q][v]);
+    }
   }
   __syncthreads();
   // vertical: item = (output column, group of 8 output rows); columns fastest
@@ -229,7 +250,9 @@ hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rh
     // clamping of the padded tile makes any radius exact; use rho itself
     dim3 grid((w + kMTX - 1) / kMTX, (h + kMTY - 1) / kMTY, b.n);
     const int EX = kMTX + 2 * rho, EY = kMTY + 2 * rho, XS = EX | 1;
-    const size_t lds = (size_t)((EY * XS + 1) & ~1) * sizeof(float) + (size_t)EY * kHS * sizeof(float2);
+    // the padded tile, then the horizontal result in the same bytes
+    const size_t tile_b = (size_t)EY * XS * sizeof(float), hres_b = (size_t)EY * kHS * sizeof(float2);
+    const size_t lds = tile_b > hres_b ? tile_b : hres_b;
     hipLaunchKernelGGL(minmax_tile, grid, dim3(kThreads), lds, stream, img, pitch, h, w, rho,
                        alpha, beta, out_pitch, b);
     return hipGetLastError();

@@ -56,7 +56,8 @@ def run_fast(torch, abf, wl, precision, **kw):
 # ----------------------------------------------------------------- bounds
 @pytest.mark.parametrize("shape,R", [((256, 256), 3), ((37, 300), 5), ((300, 37), 20), ((1, 129), 4),
                                      ((129, 1), 4), ((5, 7), 20), ((1, 1), 3), ((70, 90), 0),
-                                     ((200, 333), 96)])
+                                     ((200, 333), 96), ((64, 100), 1), ((33, 70), 2), ((65, 130), 6),
+                                     ((100, 150), 24), ((97, 200), 25)])
 def test_minmax_bit_exact(torch, abf, shape, R):
     f = rect_scene(11, *shape, n_rect=4, noise=10, side_lo=1, side_hi=max(2, min(shape)))
     a, b = abf.minmax(dev(torch, f), R)
