@@ -40,7 +40,7 @@ METRIC = "Mpix/s fast-ABF mixed vs all-FP64 on GPU at max err≤0.05/255; p50/p9
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
 DEFAULT_WORKLOAD = "sharpen1024_gauss15_n6"
-N_STREAMS = 2                  # images in flight in the timed steps
+N_STREAMS = 2                  # images in flight in the timed steps (default of --streams)
 
 
 def log(*a):
@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--streams", type=int, default=N_STREAMS,
+                    help="streams the timed steps alternate between (1 for profiling: "
+                         "kernels that overlap report stretched durations)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--parity-pixels", type=int, default=600)
@@ -171,11 +174,12 @@ def main():
     # the timed steps alternate between two streams, each with its own stack,
     # scratch and output buffers (two images in flight: one image's kernels
     # fill the other's kernel tails and launch gaps)
-    streams = [torch.cuda.Stream() for _ in range(N_STREAMS)]
+    n_streams = max(1, args.streams)
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
 
     def make_path(prec, fused):
         bufs = []
-        for _ in range(N_STREAMS):
+        for _ in range(n_streams):
             bufs.append((torch.empty(abf.stack_bytes(H, W, N, prec), dtype=torch.uint8, device="cuda"),
                          torch.empty(abf.lib().abf_scratch_bytes(H, W, R), dtype=torch.uint8, device="cuda"),
                          torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64,
@@ -220,7 +224,7 @@ def main():
         for st in streams:
             st.wait_stream(cur)
         for i in range(warmup):
-            step(i % N_STREAMS, streams[i % N_STREAMS])
+            step(i % n_streams, streams[i % n_streams])
         torch.cuda.synchronize()
         # timed region: K steps issued back to back, alternating between the
         # streams, synchronised on both sides, with no events between the
@@ -228,7 +232,7 @@ def main():
         # per kernel boundary)
         t0 = time.perf_counter()
         for i in range(steps):
-            step(i % N_STREAMS, streams[i % N_STREAMS])
+            step(i % n_streams, streams[i % n_streams])
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / steps
         # the same K steps on one stream, no events: the single-stream rate
@@ -355,7 +359,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "h": H, "w": W, "kernel": kernel, "rho": R, "N": N,
                    "sigma_s": ss, "precision": "mixed (FP64 arithmetic, FP32 stack and output)",
-                   "streams": N_STREAMS},
+                   "streams": n_streams},
         "single_stream": {"value": round(mpix / (wall1_m * 1e-3), 2), "ms_per_step": round(wall1_m, 5),
                           "fp64_value": round(mpix / (wall1_d * 1e-3), 2)},
         "latency_ms": {"p50": round(float(np.percentile(lat_m, 50)), 5),
