@@ -26,7 +26,8 @@ def abf():
     return m
 
 
-@pytest.mark.parametrize("kernel,R,N", [("box", 3, 5), ("box", 30, 6), ("gaussian", 5, 4), ("box", 2, 0)])
+@pytest.mark.parametrize("kernel,R,N", [("box", 3, 5), ("box", 30, 6), ("gaussian", 5, 4), ("box", 2, 0),
+                                         ("gaussian", 15, 6), ("gaussian", 20, 8)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_strided_equals_single_calls(torch, abf, kernel, R, N, precision):
     n, h, w = 5, 61, 97
