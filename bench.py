@@ -18,8 +18,9 @@ the Gaussian tile kernel the stack is one launch that also takes the window
 bounds. The mixed-precision path is the headline value; the
 all-FP64 path, the fused variant (abf_minmax -> abf_moments_range, moments
 and range stage in one kernel, no moment planes in HBM) and the GPU brute
-force are timed beside it, and parity against the CPU oracle is checked on
-sampled pixels.
+force are timed beside it. The cpu_baseline leg times the CPU oracle on a
+bounded sample of the workload's pixels, and its values at those pixels
+give the parity of both GPU paths (null with --no-cpu-baseline).
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -45,6 +46,24 @@ N_STREAMS = 2                  # images in flight in the timed steps (default of
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+class one_host_thread:
+    """Limits the numerical libraries to one host thread (the CPU oracle's
+    baseline is quoted per core)."""
+
+    def __enter__(self):
+        try:
+            from threadpoolctl import threadpool_limits
+            self._ctx = threadpool_limits(1)
+        except Exception:                      # pragma: no cover
+            self._ctx = None
+        return self
+
+    def __exit__(self, *exc):
+        if self._ctx is not None:
+            self._ctx.__exit__(*exc)
+        return False
 
 
 def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
@@ -124,7 +143,6 @@ def main():
                          "kernels that overlap report stretched durations)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--parity-pixels", type=int, default=600)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device-to-device copy (counter calibration for profiles)")
     ap.add_argument("--paper-maps", action="store_true",
@@ -285,19 +303,6 @@ def main():
     torch.cuda.synchronize()
     brute_ms = e0.elapsed_time(e1) / bsteps
 
-    # ---------------------------------------------------------- parity (sampled)
-    import oracle
-    rng = np.random.default_rng(7)
-    n = args.parity_pixels
-    ys = np.concatenate([rng.integers(0, H, n), [0, 0, H - 1, H - 1]])
-    xs = np.concatenate([rng.integers(0, W, n), [0, W - 1, 0, W - 1]])
-    log("oracle parity on sampled pixels ...")
-    ref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(ys, xs))
-    gm = out_m.cpu().numpy().astype(np.float64)[ys, xs]
-    gd = out_d.cpu().numpy()[ys, xs]
-    err_m = float(np.max(np.abs(gm - ref)))
-    err_d = float(np.max(np.abs(gd - ref)))
-
     # ---------------------------------------------------------- roofline
     model = stage_model(H, W, kernel, R, N, 4, th is not None)
     stages = {k: med(v) for k, v in st_m.items()}
@@ -318,30 +323,35 @@ def main():
                  "algorithmic_bytes": model[dom]["bytes"], "algorithmic_flops": model[dom]["flops"]})
 
     # ---------------------------------------------------------- CPU oracle baseline
-    cpu = None
+    # The cpu_baseline leg: the CPU oracle, one host thread, on a bounded
+    # random sample of this workload's pixels (plus the four corners), about
+    # --cpu-seconds of work. Its values at those pixels also give the GPU
+    # paths' parity (max |error| on [0, 255]); without the leg both are null.
+    cpu, err_m, err_d, n_par = None, None, None, 0
     if not args.no_cpu_baseline:
-        try:
-            from threadpoolctl import threadpool_limits
-        except Exception:                      # pragma: no cover
-            threadpool_limits = None
-        ctx = threadpool_limits(1) if threadpool_limits else None
-        try:
+        import oracle
+        rng = np.random.default_rng(7)
+        with one_host_thread():
             probe = 500
+            py = np.concatenate([[0, 0, H - 1, H - 1], rng.integers(0, H, probe)])
+            px = np.concatenate([[0, W - 1, 0, W - 1], rng.integers(0, W, probe)])
             t0 = time.perf_counter()
-            oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss,
-                            pixels=(rng.integers(0, H, probe), rng.integers(0, W, probe)))
-            per_px = (time.perf_counter() - t0) / probe
+            pref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(py, px))
+            per_px = (time.perf_counter() - t0) / len(py)
             m = int(max(probe, min(H * W, args.cpu_seconds / max(per_px, 1e-9))))
             sy, sx = rng.integers(0, H, m), rng.integers(0, W, m)
+            log(f"CPU oracle on {m} sampled pixels ...")
             t0 = time.perf_counter()
-            oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(sy, sx))
+            sref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(sy, sx))
             dt = time.perf_counter() - t0
-            cpu = {"value": round(m / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-                   "sample": f"{m} random pixels of the same {H}x{W} workload, value-of-record "
-                             f"oracle route, 1 thread, {dt:.1f} s"}
-        finally:
-            if ctx is not None:
-                ctx.__exit__(None, None, None)
+        cpu = {"value": round(m / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+               "sample": f"{m} random pixels of the same {H}x{W} workload, value-of-record "
+                         f"oracle route, 1 thread, {dt:.1f} s"}
+        ys, xs = np.concatenate([py, sy]), np.concatenate([px, sx])
+        ref = np.concatenate([pref, sref])
+        err_m = float(np.max(np.abs(out_m.cpu().numpy().astype(np.float64)[ys, xs] - ref)))
+        err_d = float(np.max(np.abs(out_d.cpu().numpy()[ys, xs] - ref)))
+        n_par = int(len(ys))
 
     lat_m = np.array(tot_m)
     res = {
@@ -369,7 +379,7 @@ def main():
                  "stage_ms": {k: round(med(v), 5) for k, v in st_d.items()},
                  "max_abs_err_vs_oracle": err_d},
         "mixed_max_abs_err_vs_oracle": err_m,
-        "parity_pixels": int(len(ys)),
+        "parity_pixels": n_par,
         "brute_force_fp64": {"value": round(mpix / (brute_ms * 1e-3), 3), "ms": round(brute_ms, 3)},
         "device_ms_per_step_median": {"mixed": round(med(tot_m), 5), "fp64": round(med(tot_d), 5)},
         "fused_variant": {"mixed_ms_per_step": round(wall_s, 5), "fp64_ms_per_step": round(wall_sd, 5),
@@ -458,9 +468,7 @@ def paper_maps_bench(args):
     import numpy as np
     import torch
 
-    import oracle
     import paper_1811_02308_amd as abf
-    from oracle import maps
     from synth import workload
 
     def timed(fn, reps):
@@ -487,19 +495,34 @@ def paper_maps_bench(args):
         return abf.fast(f, sg[0], theta=th[0], kernel="gaussian", rho=15, N=6, sigma_s=5.0,
                         out=out, workspace=ws), th, sg
     (_, th, sg), dev_ms, wall_ms = timed(sharpen, max(5, min(args.steps, 50)))
-    rng = np.random.default_rng(3)
-    ys, xs = rng.integers(0, H, 300), rng.integers(0, W, 300)
-    ref = oracle.fast_abf(sw["f"], th[0].cpu().numpy(), sg[0].cpu().numpy(), "gaussian", 15, 6,
-                          sigma_s=5.0, pixels=(ys, xs))
-    rth, rsg = maps.sharpen_maps(sw["f"][:200, :200], 15, 1.0, 5.0, 40.0, 20.0)
     res["sharpening"] = {
         "workload": "sharpen1024 field, maps from the image, Gaussian R=15 N=6, mixed",
         "ms_per_image": round(wall_ms, 4), "device_ms": round(dev_ms, 4),
         "mpix_per_s": round(H * W / 1e6 / (wall_ms * 1e-3), 1),
-        "max_abs_err_vs_oracle": float(np.max(np.abs(out.cpu().numpy().astype(np.float64)[ys, xs] - ref))),
-        "maps_max_abs_err_vs_oracle_200x200": float(max(
+        "max_abs_err_vs_oracle": None, "maps_max_abs_err_vs_oracle_200x200": None}
+    if not args.no_cpu_baseline:
+        # cpu_baseline leg: the CPU oracle (one thread) on 300 random pixels
+        # of the filter fed the GPU's maps, and the maps on a 200 x 200 crop;
+        # the same values give the parity
+        import oracle
+        from oracle import maps
+        rng = np.random.default_rng(3)
+        ys, xs = rng.integers(0, H, 300), rng.integers(0, W, 300)
+        with one_host_thread():
+            t0 = time.perf_counter()
+            ref = oracle.fast_abf(sw["f"], th[0].cpu().numpy(), sg[0].cpu().numpy(), "gaussian", 15,
+                                  6, sigma_s=5.0, pixels=(ys, xs))
+            dt = time.perf_counter() - t0
+            rth, rsg = maps.sharpen_maps(sw["f"][:200, :200], 15, 1.0, 5.0, 40.0, 20.0)
+        res["sharpening"]["max_abs_err_vs_oracle"] = float(
+            np.max(np.abs(out.cpu().numpy().astype(np.float64)[ys, xs] - ref)))
+        res["sharpening"]["maps_max_abs_err_vs_oracle_200x200"] = float(max(
             np.max(np.abs(th[0].cpu().numpy()[:200, :200] - rth)[20:-20, 20:-20]),
-            np.max(np.abs(sg[0].cpu().numpy()[:200, :200] - rsg)[20:-20, 20:-20])))}
+            np.max(np.abs(sg[0].cpu().numpy()[:200, :200] - rsg)[20:-20, 20:-20])))
+        res["cpu_baseline"] = {"value": round(len(ys) / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{len(ys)} random pixels of the sharpening filter, 1 thread, "
+                                         f"{dt:.1f} s"}
     log("sharpening:", res["sharpening"])
     tw = workload("texture1080_box8_n6")
     n3, h, w = tw["frames"].shape
@@ -546,21 +569,33 @@ def texture_bench(args):
     out_m, ms_m, dev_m = run("mixed", steps, 1)
     out_d, ms_d, dev_d = run("fp64", steps, 1)
     mpix = passes * n * H * W / 1e6
-    # parity of the last pass on sampled pixels of three planes: feed the
-    # oracle the GPU's own pass input and sigma map
-    import oracle
-    rng = np.random.default_rng(5)
-    errs = {"mixed": 0.0, "fp64": 0.0}
-    for prec in ("mixed", "fp64"):
-        prev = abf.texture_filter(x, passes - 1, R, N, precision=prec, **sr).float() if passes > 1 else x
-        sig = abf.sigma_local_std(prev, **sr)
-        last = abf.fast_strided(prev, sig, kernel="box", rho=R, N=N, precision=prec)
-        for c in (0, n // 2, n - 1):
-            ys, xs = rng.integers(0, H, 150), rng.integers(0, W, 150)
-            ref = oracle.fast_abf(prev[c].cpu().numpy(), None, sig[c].cpu().numpy(), "box", R, N,
-                                  pixels=(ys, xs))
-            got = last[c].cpu().numpy().astype(np.float64)[ys, xs]
-            errs[prec] = max(errs[prec], float(np.max(np.abs(got - ref))))
+    # cpu_baseline leg: the CPU oracle (one thread) on sampled pixels of the
+    # last pass of three planes, fed the GPU's own pass input and sigma map;
+    # the same values give the parity
+    errs = {"mixed": None, "fp64": None}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(5)
+        npx, tsum = 0, 0.0
+        for prec in ("mixed", "fp64"):
+            prev = abf.texture_filter(x, passes - 1, R, N, precision=prec, **sr).float() if passes > 1 else x
+            sig = abf.sigma_local_std(prev, **sr)
+            last = abf.fast_strided(prev, sig, kernel="box", rho=R, N=N, precision=prec)
+            errs[prec] = 0.0
+            for c in (0, n // 2, n - 1):
+                ys, xs = rng.integers(0, H, 150), rng.integers(0, W, 150)
+                pc, sc = prev[c].cpu().numpy(), sig[c].cpu().numpy()
+                with one_host_thread():
+                    t0 = time.perf_counter()
+                    ref = oracle.fast_abf(pc, None, sc, "box", R, N, pixels=(ys, xs))
+                    tsum += time.perf_counter() - t0
+                npx += len(ys)
+                got = last[c].cpu().numpy().astype(np.float64)[ys, xs]
+                errs[prec] = max(errs[prec], float(np.max(np.abs(got - ref))))
+        cpu = {"value": round(npx / tsum / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+               "sample": f"{npx} random pixels of the last pass (3 planes, both precisions' inputs), "
+                         f"1 thread, {tsum:.1f} s"}
     res = {"metric": METRIC, "value": round(mpix / (ms_m * 1e-3), 2), "unit": "Mpix/s", "n_gpus": 1,
            "steps": steps, "warmup": 1, "ms_per_step": round(ms_m, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -569,7 +604,7 @@ def texture_bench(args):
            "device_ms_per_step": round(dev_m, 4),
            "fp64": {"value": round(mpix / (ms_d * 1e-3), 2), "ms_per_step": round(ms_d, 4),
                     "max_abs_err_vs_oracle": errs["fp64"]},
-           "mixed_max_abs_err_vs_oracle": errs["mixed"], "roofline": None, "cpu_baseline": None}
+           "mixed_max_abs_err_vs_oracle": errs["mixed"], "roofline": None, "cpu_baseline": cpu}
     print(json.dumps(res), flush=True)
 
 
