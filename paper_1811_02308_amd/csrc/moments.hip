@@ -8,13 +8,15 @@
 // mid_i = (alpha_i + beta_i)/2, half_i = (beta_i - alpha_i)/2. This equals
 // sum_r ell_kr mu_r for the mu_r of eq. (hist_moments_new).
 //
-// Numerics. Power sums are FP64 and taken about a per-wave origin c (the
-// mid-range of the window bounds sampled over the wave's tile) instead of
-// 0, which shrinks the binomial shift's cancellation: its error grows like
-// rho^k, rho = (|mid_i - c| + half_i) / half_i, times the rounding of the
-// sums. A pixel whose rho^N exceeds a precision-dependent limit (nearly flat
-// windows far from c) is recomputed directly from its window by the whole
-// wave, so the stack is accurate for every input.
+// Numerics. Power sums are FP64 and taken about a local origin c instead
+// of 0 (box and matrix-core kernels: the mid-range of the window bounds
+// sampled over the wave's region; tile kernel: the tile's central input
+// value), which shrinks the binomial shift's cancellation: its error grows
+// like rho^k, rho = (|mid_i - c| + half_i) / half_i, times the rounding of
+// the sums. A pixel whose rho^N exceeds a limit set by the stack's precision
+// and the degree (nearly flat windows far from c) is finished about another
+// origin (the tile kernel's later passes, FP64 at N >= 7) or recomputed
+// directly from its window, so the stack is accurate for every input.
 //
 // Work decomposition (box kernel). One wave owns a strip of 256 padded
 // columns (4 consecutive columns per lane) and a segment of TH output rows.
@@ -484,77 +486,6 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
   }
 }
 
-template <int N, typename TS>
-__global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
-    const float* __restrict__ img, long long pitch, int H, int W, int R, double inv2s2,
-    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long plane, StripGeom g, double cond_max) {
-  __shared__ double sh[kWaves][N][kStrip];
-  __shared__ double wts[2 * kRhoMax + 1];
-  for (int i = threadIdx.x; i <= 2 * R; i += blockDim.x) {
-    const double d = (double)(i - R);
-    wts[i] = exp(-d * d * inv2s2);
-  }
-  __syncthreads();
-  double z = 0.0;
-  for (int i = 0; i <= 2 * R; ++i) z += wts[i];
-  const double iz = 1.0 / z;       // 1-D normalisation (2-D weight = product)
-
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
-  const int gw = blockIdx.x * kWaves + wv;
-  if (gw >= g.n_strips * g.n_segs) return;
-  const int strip = gw % g.n_strips;
-  const int seg = gw / g.n_strips;
-  const int y0 = seg * g.TH;
-  const int y1 = min(H, y0 + g.TH);
-  const int xo = strip * g.O;
-  const int xs = xo - g.Rpad;
-  const double c = wave_origin(alpha, beta, sp, y0, y1, xo, g.O, W, lane);
-
-  int cx[kV];
-#pragma unroll
-  for (int v = 0; v < kV; ++v) cx[v] = min(max(xs + kV * lane + v, 0), W - 1);
-
-  for (int y = y0; y < y1; ++y) {
-    double S[N][kV];
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-#pragma unroll
-      for (int v = 0; v < kV; ++v) S[k][v] = 0.0;
-    for (int dy = -R; dy <= R; ++dy) {
-      const float* row = img + (long long)min(max(y + dy, 0), H - 1) * pitch;
-      const double wy = wts[dy + R] * iz;
-#pragma unroll
-      for (int v = 0; v < kV; ++v) {
-        const double u = (double)row[cx[v]] - c;
-        double p = u;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          S[k][v] = fma(wy, p, S[k][v]);
-          p *= u;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-#pragma unroll
-      for (int v = 0; v < kV; ++v) sh[wv][k][kV * lane + v] = S[k][v];
-    wave_sync();
-    auto sum_k = [&](int j, int k) -> double {
-      const int e = g.Rpad + j;
-      double acc = 0.0;
-      for (int dx = -R; dx <= R; ++dx) acc = fma(wts[dx + R], sh[wv][k][e + dx], acc);
-      return acc * iz;
-    };
-    float pa[kChunks], pb[kChunks];
-    load_bounds_row(alpha, beta, sp, y, xo, g.O, W, lane, pa, pb);
-    epilogue_row<N, TS, false>(sum_k, y, xo, g.O, W, H, R, img, pitch, pa, pb, sp, c,
-                               cond_max, wts, iz * iz, mom, plane, lane, FuseArgs{});
-    wave_sync();
-  }
-}
-
 // Gaussian kernel, tiled: a workgroup computes a kTY x TX tile of outputs.
 // (Tile sizes keep the LDS tile at 30-40 KiB so that four workgroups share a
 // CU.)
@@ -577,6 +508,7 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_gauss(
 constexpr int kTY = 4;   // output rows per tile
 constexpr int kCB = 2;   // adjacent output columns per thread in the horizontal phase
 constexpr int kPF = 8;   // input rows per prefetch chunk in the vertical phase
+constexpr int kTilePasses = 4;   // origins per tile (then the direct recompute)
 
 // doubles of LDS for the zero-padded tap weights (taps -(kTY-1) .. 2R+kTY-1),
 // rounded up to an even count so that what follows stays 16-byte aligned
@@ -657,174 +589,223 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   }
   __syncthreads();
   const double iz = inv_z;
-  const double c = (double)cval;
+  const double norm = iz * iz;
+  double c = (double)cval;
 
-  // phase 1: vertical sums for padded column tc. The column's inputs are
-  // read in chunks of kPF rows, the next chunk's loads issued before the
-  // current chunk is used, so memory latency overlaps the arithmetic.
-  if (tc < E) {
-    double acc[kTY][N];
+  // phase 2/3 role: kCB adjacent output columns xl .. of output row r
+  const int groups = TX / kCB;
+  const int r = t / groups, gq = t - r * groups;
+  const bool active = r < kTY;
+  const int xl = kCB * gq;
+  float pa[kCB], pb[kCB];           // the outputs' window bounds
+  bool pend[kCB];                   // ill-conditioned about every origin so far
 #pragma unroll
-    for (int r = 0; r < kTY; ++r)
+  for (int v = 0; v < kCB; ++v) {
+    pa[v] = 0.f;
+    pb[v] = 0.f;
+    pend[v] = false;
+  }
+  __shared__ int next_pick;
+  __shared__ double next_origin;
+
+  // Pass p takes the power sums about origin c and finishes every pixel
+  // (after the first pass: every pending pixel) whose shift is well
+  // conditioned about it; the next origin is the window mid-range of the
+  // first pixel still pending. Pixels still ill-conditioned in the last
+  // pass are recomputed directly. Only the FP64 path at N >= 7 takes more
+  // than one pass (its threshold flags many pixels on high-contrast
+  // content); a single pass keeps the kernel at half the registers.
+  constexpr int kPasses = (sizeof(TS) == 8 && N >= 7) ? kTilePasses : 1;
+#pragma unroll 1
+  for (int pass_ = 0; pass_ < kPasses; ++pass_) {
+    const int pass = kPasses == 1 ? 0 : pass_;     // constants when there is one pass
+    const bool first = pass == 0, last = kPasses == 1 || pass == kPasses - 1;
+    // phase 1: vertical sums for padded column tc. The column's inputs are
+    // read in chunks of kPF rows, the next chunk's loads issued before the
+    // current chunk is used, so memory latency overlaps the arithmetic.
+    if (tc < E) {
+      if (!first) load_chunk(0, qn);
+      double acc[kTY][N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) acc[r][k] = 0.0;
-    // BOUNDS: min/max of the inputs shared by every row's window (cmn, cmx)
-    // and of each row's other inputs (mn, mx)
-    float cmn = INFINITY, cmx = -INFINITY, mn[kTY], mx[kTY];
+      for (int rr = 0; rr < kTY; ++rr)
 #pragma unroll
-    for (int r = 0; r < kTY; ++r) {
-      mn[r] = INFINITY;
-      mx[r] = -INFINITY;
-    }
-    for (int i0 = 0; i0 < n_in; i0 += kPF) {
-      float q[kPF];
+        for (int k = 0; k < N; ++k) acc[rr][k] = 0.0;
+      // BOUNDS (first pass): min/max of the inputs shared by every row's
+      // window (cmn, cmx) and of each row's other inputs (mn, mx)
+      float cmn = INFINITY, cmx = -INFINITY, mn[kTY], mx[kTY];
 #pragma unroll
-      for (int p = 0; p < kPF; ++p) q[p] = qn[p];
-      if (i0 + kPF < n_in) load_chunk(i0 + kPF, qn);
+      for (int rr = 0; rr < kTY; ++rr) {
+        mn[rr] = INFINITY;
+        mx[rr] = -INFINITY;
+      }
+      for (int i0 = 0; i0 < n_in; i0 += kPF) {
+        float q[kPF];
 #pragma unroll
-      for (int p = 0; p < kPF; ++p) {
-        const int i = i0 + p;
-        if (i < n_in) {
-          const double u = (double)q[p] - c;
-          double pw[N];
-          pw[0] = u;
+        for (int p = 0; p < kPF; ++p) q[p] = qn[p];
+        if (i0 + kPF < n_in) load_chunk(i0 + kPF, qn);
 #pragma unroll
-          for (int k = 1; k < N; ++k) pw[k] = pw[k - 1] * u;
-          // output row r takes tap i - r (a zero weight outside [0, 2R])
+        for (int p = 0; p < kPF; ++p) {
+          const int i = i0 + p;
+          if (i < n_in) {
+            const double u = (double)q[p] - c;
+            double pw[N];
+            pw[0] = u;
 #pragma unroll
-          for (int r = 0; r < kTY; ++r) {
-            const double wv = wts[i - r];
+            for (int k = 1; k < N; ++k) pw[k] = pw[k - 1] * u;
+            // output row rr takes tap i - rr (a zero weight outside [0, 2R])
 #pragma unroll
-            for (int k = 0; k < N; ++k) acc[r][k] = fma(wv, pw[k], acc[r][k]);
+            for (int rr = 0; rr < kTY; ++rr) {
+              const double wv = wts[i - rr];
+#pragma unroll
+              for (int k = 0; k < N; ++k) acc[rr][k] = fma(wv, pw[k], acc[rr][k]);
+            }
+            if (BOUNDS && first) {
+              const float v = q[p] + 0.0f;     // -0 -> +0, as the bounds kernel
+              if (i >= kTY - 1 && i <= 2 * R) {
+                cmn = fminf(cmn, v);
+                cmx = fmaxf(cmx, v);
+              } else {
+#pragma unroll
+                for (int rr = 0; rr < kTY; ++rr)
+                  if (i >= rr && i <= rr + 2 * R) {
+                    mn[rr] = fminf(mn[rr], v);
+                    mx[rr] = fmaxf(mx[rr], v);
+                  }
+              }
+            }
           }
-          if (BOUNDS) {
-            const float v = q[p] + 0.0f;     // -0 -> +0, as the bounds kernel
-            if (i >= kTY - 1 && i <= 2 * R) {
-              cmn = fminf(cmn, v);
-              cmx = fmaxf(cmx, v);
-            } else {
+        }
+      }
 #pragma unroll
-              for (int r = 0; r < kTY; ++r)
-                if (i >= r && i <= r + 2 * R) {
-                  mn[r] = fminf(mn[r], v);
-                  mx[r] = fmaxf(mx[r], v);
-                }
+      for (int rr = 0; rr < kTY; ++rr)
+#pragma unroll
+        for (int k = 0; k < N; ++k) vsum[(k * kTY + rr) * ES + tc] = acc[rr][k];
+      if (BOUNDS && first) {
+#pragma unroll
+        for (int rr = 0; rr < kTY; ++rr)
+          vmm[rr * ES + tc] = make_float2(fminf(mn[rr], cmn), fmaxf(mx[rr], cmx));
+      }
+    }
+    __syncthreads();
+
+    // phase 2: horizontal sums for kCB adjacent outputs of one row. The
+    // (kCB + 2R) LDS columns a thread spans are read as 16-byte pairs: the
+    // pairs of neighbouring lanes are contiguous, so the reads are free of
+    // bank conflicts (ES, 2R and the thread's first column are even).
+    // Column cc (relative to the thread's first) feeds output v at tap cc - v.
+    double m4[kCB][N + 1];
+    if (active) {
+      // BOUNDS: window min/max of the outputs; columns kCB - 1 .. 2R are in
+      // every output's window (hmn, hmx), the others in some of them
+      float bmn[kCB], bmx[kCB];
+#pragma unroll
+      for (int v = 0; v < kCB; ++v) {
+        bmn[v] = INFINITY;
+        bmx[v] = -INFINITY;
+      }
+#pragma unroll
+      for (int v = 0; v < kCB; ++v)
+#pragma unroll
+        for (int k = 0; k <= N; ++k) m4[v][k] = 0.0;
+      float hmn = INFINITY, hmx = -INFINITY;
+      const double2* vs2 = reinterpret_cast<const double2*>(vsum);
+      const float4* vm4 = reinterpret_cast<const float4*>(vmm);
+      auto take = [&](int cc, float lo, float hi) {
+        if (cc >= kCB - 1 && cc <= 2 * R) {
+          hmn = fminf(hmn, lo);
+          hmx = fmaxf(hmx, hi);
+        } else {
+#pragma unroll
+          for (int v = 0; v < kCB; ++v)
+            if (cc >= v && cc <= v + 2 * R) {
+              bmn[v] = fminf(bmn[v], lo);
+              bmx[v] = fmaxf(bmx[v], hi);
+            }
+        }
+      };
+      for (int j = 0; j < kCB + 2 * R; j += 2) {
+        double2 val[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) val[k] = vs2[((k * kTY + r) * ES + xl + j) >> 1];
+        if (BOUNDS && first) {
+          // (min, max) of columns xl + j and xl + j + 1
+          const float4 qm = vm4[(r * ES + xl + j) >> 1];
+          take(j, qm.x, qm.y);
+          take(j + 1, qm.z, qm.w);
+        }
+        double wa[kCB], wb[kCB];      // taps j - v and j + 1 - v (0 outside [0, 2R])
+#pragma unroll
+        for (int v = 0; v < kCB; ++v) {
+          wa[v] = wts[j - v];
+          wb[v] = wts[j + 1 - v];
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+#pragma unroll
+          for (int v = 0; v < kCB; ++v) {
+            m4[v][k + 1] = fma(wa[v], val[k].x, m4[v][k + 1]);
+            m4[v][k + 1] = fma(wb[v], val[k].y, m4[v][k + 1]);
+          }
+      }
+      if (first) {
+#pragma unroll
+        for (int v = 0; v < kCB; ++v) {
+          const int y = y0 + r, x = x0 + xl + v;
+          if (y < H && x < W && xl + v < TX) {
+            const long long idx = (long long)y * sp + x;
+            if (BOUNDS) {
+              pa[v] = fminf(bmn[v], hmn);
+              pb[v] = fmaxf(bmx[v], hmx);
+              alpha[idx] = pa[v];
+              beta[idx] = pb[v];
+            } else {
+              pa[v] = alpha[idx];
+              pb[v] = beta[idx];
             }
           }
         }
       }
     }
-#pragma unroll
-    for (int r = 0; r < kTY; ++r)
-#pragma unroll
-      for (int k = 0; k < N; ++k) vsum[(k * kTY + r) * ES + tc] = acc[r][k];
-    if (BOUNDS) {
-#pragma unroll
-      for (int r = 0; r < kTY; ++r)
-        vmm[r * ES + tc] = make_float2(fminf(mn[r], cmn), fmaxf(mx[r], cmx));
-    }
-  }
-  __syncthreads();
-
-  // phase 2: horizontal sums for kCB adjacent outputs of one row. The
-  // (kCB + 2R) LDS columns a thread spans are read as 16-byte pairs: the
-  // pairs of neighbouring lanes are contiguous, so the reads are free of
-  // bank conflicts (ES, 2R and the thread's first column are even). Column
-  // c (relative to the thread's first) feeds output v at tap c - v.
-  const int groups = TX / kCB;
-  const int r = t / groups, gq = t - r * groups;
-  const bool active = r < kTY;
-  const int xl = kCB * gq;
-  double m4[kCB][N + 1];
-  // BOUNDS: window min/max of the outputs; columns kCB - 1 .. 2R are in
-  // every output's window (hmn, hmx), the others in some of them
-  float bmn[kCB], bmx[kCB];
-#pragma unroll
-  for (int v = 0; v < kCB; ++v) {
-    bmn[v] = INFINITY;
-    bmx[v] = -INFINITY;
-  }
-  if (active) {
-#pragma unroll
-    for (int v = 0; v < kCB; ++v)
-#pragma unroll
-      for (int k = 0; k <= N; ++k) m4[v][k] = 0.0;
-    float hmn = INFINITY, hmx = -INFINITY;
-    const double2* vs2 = reinterpret_cast<const double2*>(vsum);
-    const float4* vm4 = reinterpret_cast<const float4*>(vmm);
-    auto take = [&](int c, float lo, float hi) {
-      if (c >= kCB - 1 && c <= 2 * R) {
-        hmn = fminf(hmn, lo);
-        hmx = fmaxf(hmx, hi);
-      } else {
-#pragma unroll
-        for (int v = 0; v < kCB; ++v)
-          if (c >= v && c <= v + 2 * R) {
-            bmn[v] = fminf(bmn[v], lo);
-            bmx[v] = fmaxf(bmx[v], hi);
-          }
-      }
-    };
-    for (int j = 0; j < kCB + 2 * R; j += 2) {
-      double2 val[N];
-#pragma unroll
-      for (int k = 0; k < N; ++k) val[k] = vs2[((k * kTY + r) * ES + xl + j) >> 1];
-      if (BOUNDS) {
-        // (min, max) of columns xl + j and xl + j + 1
-        const float4 q = vm4[(r * ES + xl + j) >> 1];
-        take(j, q.x, q.y);
-        take(j + 1, q.z, q.w);
-      }
-      double wa[kCB], wb[kCB];        // taps j - v and j + 1 - v (0 outside [0, 2R])
-#pragma unroll
-      for (int v = 0; v < kCB; ++v) {
-        wa[v] = wts[j - v];
-        wb[v] = wts[j + 1 - v];
-      }
-#pragma unroll
-      for (int k = 0; k < N; ++k)
-#pragma unroll
-        for (int v = 0; v < kCB; ++v) {
-          m4[v][k + 1] = fma(wa[v], val[k].x, m4[v][k + 1]);
-          m4[v][k + 1] = fma(wb[v], val[k].y, m4[v][k + 1]);
-        }
-    }
+    // phase 3: per-pixel epilogue (all lanes take part in the wave ballots)
+    bool anyp = false;
 #pragma unroll
     for (int v = 0; v < kCB; ++v) {
-      bmn[v] = fminf(bmn[v], hmn);
-      bmx[v] = fmaxf(bmx[v], hmx);
-    }
-  }
-  // phase 3: per-pixel epilogue (all lanes take part in the wave ballots)
-  const double norm = iz * iz;
+      const int y = y0 + r, x = x0 + xl + v;
+      const bool valid = active && y < H && x < W && xl + v < TX;
+      const bool want = valid && (first || pend[v]);
+      const long long idx = (long long)(valid ? y : 0) * sp + (valid ? x : 0);
+      bool bad = false;
+      if (want) {
+        double m[N + 1];
+        m[0] = 1.0;
 #pragma unroll
-  for (int v = 0; v < kCB; ++v) {
-    const int y = y0 + r, x = x0 + xl + v;
-    const bool valid = active && y < H && x < W && xl + v < TX;
-    const long long idx = (long long)(valid ? y : 0) * sp + (valid ? x : 0);
-    float a = 0.f, b = 0.f;
-    bool bad = false;
-    if (valid) {
-      double m[N + 1];
-      m[0] = 1.0;
-#pragma unroll
-      for (int k = 1; k <= N; ++k) m[k] = m4[v][k] * norm;
-      if (BOUNDS) {
-        a = bmn[v];
-        b = bmx[v];
-        alpha[idx] = a;
-        beta[idx] = b;
-      } else {
-        a = alpha[idx];
-        b = beta[idx];
+        for (int k = 1; k <= N; ++k) m[k] = m4[v][k] * norm;
+        bad = legendre_from_moments<N>(m, pa[v], pb[v], c, cond_max);
+        if (!bad) finish_pixel<N, TS, FUSED>(m, pa[v], pb[v], y, x, idx, mom, plane, fz);
+        pend[v] = bad && !last;
       }
-      bad = legendre_from_moments<N>(m, a, b, c, cond_max);
-      if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
+      anyp = anyp || pend[v];
+      const unsigned long long mask = __ballot(want && bad && last);
+      if (mask)
+        recompute_flagged<N, TS, FUSED>(mask, want && bad && last, y, x, pa[v], pb[v], img, pitch, H,
+                                        W, R, wts, norm, mom, plane, sp, lane, fz);
     }
-    const unsigned long long mask = __ballot(valid && bad);
-    if (mask)
-      recompute_flagged<N, TS, FUSED>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm,
-                                      mom, plane, sp, lane, fz);
+    if (kPasses == 1) break;
+    // the next origin: the window mid-range of the first pending pixel (the
+    // barrier also keeps this pass's LDS reads ahead of the next pass's writes)
+    if (!__syncthreads_or(anyp)) break;
+    if (t == 0) next_pick = 0x7fffffff;
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < kCB; ++v)
+      if (pend[v]) atomicMin(&next_pick, r * TX + xl + v);
+    __syncthreads();
+    const int pk = next_pick;
+#pragma unroll
+    for (int v = 0; v < kCB; ++v)
+      if (pend[v] && r * TX + xl + v == pk) next_origin = 0.5 * ((double)pa[v] + (double)pb[v]);
+    __syncthreads();
+    c = next_origin;
   }
 }
 
@@ -1063,11 +1044,16 @@ int device_cus() {
   return cus;
 }
 
+// Shift amplification tolerated by the FP64 path, by degree.
+constexpr double fp64_cond_max(int N) { return N <= 5 ? 1e8 : (N == 6 ? 1e6 : 1e4); }
+
 // The matrix-core kernel is the faster one for wide windows on large
 // images (measured: at 2048^2 and 4096^2 with 8 <= R <= 16 it takes 0.8-0.95
 // of the tile kernel's time; at 1024^2 they tie, below that it is slower).
-bool gauss_on_mfma(int R, long long h, long long w) {
-  return R <= kMfmaRMax && R >= 8 && h * w >= (1LL << 22);
+// Degrees 7 and 8 stay on the tile kernel, whose re-origin passes keep
+// their ill-conditioned pixels cheap.
+bool gauss_on_mfma(int R, int N, long long h, long long w) {
+  return R <= kMfmaRMax && R >= 8 && N <= 6 && h * w >= (1LL << 22);
 }
 
 template <int N, typename TS>
@@ -1088,10 +1074,20 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     return (long long)blocks * kWaves * device_cus();
   }();
   const StripGeom g = make_geom(h, w, R, capacity);
-  // largest tolerated shift amplification: FP64 stack keeps ~1e-8 relative
-  // headroom; the FP32 stack only needs to stay below its own rounding
-  const double cond_max = sizeof(TS) == 8 ? 1e8 : 1e12;
+  // largest tolerated shift amplification rho^N before a pixel is taken
+  // about another origin (or recomputed): the FP32 stack only needs to stay
+  // below its own rounding; the FP64 path's 1e-6 bound was checked pixel
+  // by pixel on 4096^2 images with clipped, high-contrast regions, where the
+  // shift's rounding (amplified further by the Legendre coefficients, which
+  // grow with N) needed rho^N <= 1e4 at N = 8
+  const double cond_max = sizeof(TS) == 4 ? 1e12 : fp64_cond_max(N);
   const int waves = g.n_strips * g.n_segs;
+  // The box kernel's running sums add and remove every row of a strip
+  // segment, so their rounding follows the largest values the strip holds,
+  // not the pixel's window: too much for the FP64 path at N >= 7 on
+  // high-contrast images. That case takes the tile kernel with unit
+  // weights (direct sums over each window, and its re-origin passes).
+  const bool box_tile = kind == 0 && sizeof(TS) == 8 && N >= 7;
   FuseArgs fz{};
   if (fs) {
     fz.theta = fs->theta;
@@ -1103,7 +1099,7 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     fz.keep_stack = fs->keep_stack;
     fz.gl = make_gl_args(sizeof(TS) == 4);
   }
-  if (kind == 0) {
+  if (kind == 0 && !box_tile) {
     dim3 grid((waves + kWaves - 1) / kWaves, b.n);
     const int vec4 = (pitch % 4 == 0) && (b.img % 4 == 0) &&
                      (reinterpret_cast<uintptr_t>(img) % 16 == 0);
@@ -1116,7 +1112,7 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     return hipGetLastError();
   }
   const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
-  if (!fs && gauss_on_mfma(R, h, w)) {
+  if (!fs && !box_tile && gauss_on_mfma(R, N, h, w)) {
     // strips of 16 columns; segment height a multiple of 16, chosen so the
     // grid has about two waves per SIMD (8 per CU)
     const int n_strips = (w + 15) / 16;
@@ -1135,7 +1131,8 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   const int tx = gauss_tile_tx(R, N);
   if (tx > 0) {
     dim3 tg((w + tx - 1) / tx, (h + kTY - 1) / kTY, b.n);
-    const double i2 = 1.0 / (2.0 * s * s);
+    // 1/(2 sigma_s^2); 0 makes every tap's weight exp(0) = 1 (box)
+    const double i2 = box_tile ? 0.0 : 1.0 / (2.0 * s * s);
     // LDS row stride: kESNarrow when the padded tile fits, else 256
     // (tx + 2R <= 256 by the choice of tx)
     const bool narrow = tx + 2 * R <= kESNarrow;
@@ -1156,14 +1153,8 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
 #undef ABF_TILE
     return hipGetLastError();
   }
-  if (fs) return hipErrorNotSupported;   // callers check moments_fusable() first
-  dim3 grid((waves + kWaves - 1) / kWaves);
-  for (int z = 0; z < b.n; ++z)
-    hipLaunchKernelGGL((moments_gauss<N, TS>), grid, dim3(kWaves * kWave), 0, stream,
-                       img + z * b.img, pitch, h, w, R, 1.0 / (2.0 * s * s),
-                       byte_offset(alpha, z * b.stack), byte_offset(beta, z * b.stack), sp,
-                       byte_offset(mom, z * b.stack), plane, g, cond_max);
-  return hipGetLastError();
+  // (the tile fits every radius up to ABF_RHO_MAX: tx >= 64 for N <= 8)
+  return hipErrorInvalidValue;
 }
 
 template <typename TS>
@@ -1199,7 +1190,7 @@ bool moments_take_bounds(int kernel_kind, int rho, int N, long long h, long long
   // pairs, (N + 1) kTY ES 8 bytes, plus the weights, is at most 74 KiB, so
   // two workgroups still share a CU's 160 KiB, as without the pairs); the
   // box and matrix-core kernels read the bounds from the stack
-  if (kernel_kind != 1 || N < 1 || N > 8 || gauss_on_mfma(rho, h, w)) return false;
+  if (kernel_kind != 1 || N < 1 || N > 8 || gauss_on_mfma(rho, N, h, w)) return false;
   const int tx = gauss_tile_tx(rho, N);
   const int es = tx + 2 * rho <= kESNarrow ? kESNarrow : 256;
   return tx > 0 && ((N + 1) * kTY * es + tile_wext_len(rho)) * 8 + 64 <= 81920;
@@ -1210,7 +1201,7 @@ bool moments_fusable(int kernel_kind, int rho, int N, long long h, long long w) 
   // the matrix-core kernel the fused call takes the stack path, so that its
   // output stays identical to abf_stack_moments + abf_range.
   return N >= 1 && N <= 8 &&
-         (kernel_kind == 0 || (!gauss_on_mfma(rho, h, w) && gauss_tile_tx(rho, N) > 0));
+         (kernel_kind == 0 || (!gauss_on_mfma(rho, N, h, w) && gauss_tile_tx(rho, N) > 0));
 }
 
 }  // namespace abf
