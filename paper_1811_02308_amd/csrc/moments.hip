@@ -554,23 +554,60 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * kTY;
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1);
-  const int tc = t;                    // phase 1: padded column tc
   // loads that depend on nothing else go out before the weights are formed:
   // the tile's central input value (the origin of the power sums; one
   // cache line for the whole workgroup) and the first rows of the column
   const int yc = min(y0 + kTY / 2, H - 1), xc = min(x0 + TX / 2, W - 1);
   const float cval = img[(long long)yc * pitch + xc];
-  const int n_in = kTY + 2 * R;
+  // Phase 1 roles: thread t sums padded column tc = t over all n_in input
+  // rows. When the last, partial wave would hold at most 32 columns, it
+  // takes each of them twice instead (the split wave): lanes 0..31 sum the
+  // top half of the rows, lanes 32..63 the bottom half in reverse order, and
+  // the halves are added across lanes, so that wave runs half the rows.
+  // Reversed, the bottom half's row ii meets output row kTY-1-s at tap
+  // 2R - (ii - s), whose weight equals that of tap ii - s (the weights are
+  // symmetric), and it lies in that row's window exactly when the top
+  // half's row ii lies in row s's: so both halves run the same wave-uniform
+  // code, the bottom half holding output row rr in accumulator slot kTY-1-rr.
+  static_assert(kTY % 2 == 0, "the split wave pairs slots rr and kTY-1-rr");
+  const int n_in = kTY + 2 * R;      // even
+  const int fw = E / kWave, tw = E - fw * kWave;
+  // The split is compiled for the narrow LDS stride only (R <= 16, where the
+  // tail is 2R <= 32 columns), and not into the multi-pass instantiations,
+  // whose registers are already at the limit. sw is wave-uniform and taken
+  // from the first lane, so the compiler branches on a scalar instead of
+  // running both roles under lane masks.
+  constexpr bool kSplit = ES == kESNarrow && !(sizeof(TS) == 8 && N >= 7);
+  const bool sw = kSplit && __builtin_amdgcn_readfirstlane(tw > 0 && tw <= kWave / 2 &&
+                                                 (fw + 1) * kWave <= (int)blockDim.x &&
+                                                 t / kWave == fw) != 0;
+  const int tc = sw ? fw * kWave + (lane & (kWave / 2 - 1)) : t;
+  const bool rev = sw && lane >= kWave / 2;
+  const bool col_ok = sw ? (lane & (kWave / 2 - 1)) < tw : t < E;
   const float* col = img + min(max(x0 - R + tc, 0), W - 1);
-  auto load_chunk = [&](int i0, float (&q)[kPF]) {
+  // rows i0 .. i0 + PF - 1 of the thread's range (SW: the split wave, which
+  // prefetches half as many rows at a time to hold fewer registers)
+  auto load_chunk = [&](auto sw_c, int i0, float (&q)[kPF]) {
+    constexpr bool SW = decltype(sw_c)::value;
+    constexpr int PF = SW ? kPF / 2 : kPF;
+    const int nr = SW ? n_in / 2 : n_in;
 #pragma unroll
-    for (int p = 0; p < kPF; ++p) {
-      const int i = min(i0 + p, n_in - 1);
+    for (int p = 0; p < PF; ++p) {
+      const int ii = min(i0 + p, nr - 1);
+      const int i = (SW && rev) ? n_in - 1 - ii : ii;
       q[p] = col[(long long)min(max(y0 - R + i, 0), H - 1) * pitch];
     }
   };
   float qn[kPF];
-  if (tc < E) load_chunk(0, qn);
+  if constexpr (kSplit) {
+    if (sw) {
+      if (col_ok) load_chunk(std::true_type{}, 0, qn);
+    } else {
+      if (col_ok) load_chunk(std::false_type{}, 0, qn);
+    }
+  } else {
+    if (col_ok) load_chunk(std::false_type{}, 0, qn);
+  }
   for (int i = t; i < 2 * R + 2 * kTY - 1; i += blockDim.x) {
     const int tap = i - (kTY - 1);
     const double d = (double)(tap - R);
@@ -623,8 +660,109 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
     // phase 1: vertical sums for padded column tc. The column's inputs are
     // read in chunks of kPF rows, the next chunk's loads issued before the
     // current chunk is used, so memory latency overlaps the arithmetic.
-    if (tc < E) {
-      if (!first) load_chunk(0, qn);
+    auto vertical = [&](auto sw_c) {
+      constexpr bool SW = decltype(sw_c)::value;
+      const int nr = SW ? n_in / 2 : n_in;     // rows this thread sums
+      if (!first) load_chunk(sw_c, 0, qn);
+      double acc[kTY][N];
+#pragma unroll
+      for (int rr = 0; rr < kTY; ++rr)
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc[rr][k] = 0.0;
+      // BOUNDS (first pass): min/max of the inputs shared by every row's
+      // window (cmn, cmx) and of each row's other inputs (mn, mx)
+      float cmn = INFINITY, cmx = -INFINITY, mn[kTY], mx[kTY];
+#pragma unroll
+      for (int rr = 0; rr < kTY; ++rr) {
+        mn[rr] = INFINITY;
+        mx[rr] = -INFINITY;
+      }
+      constexpr int PF = SW ? kPF / 2 : kPF;
+      for (int i0 = 0; i0 < nr; i0 += PF) {
+        float q[PF];
+#pragma unroll
+        for (int p = 0; p < PF; ++p) q[p] = qn[p];
+        if (i0 + PF < nr) load_chunk(sw_c, i0 + PF, qn);
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+          const int i = i0 + p;      // (the bottom half: row n_in - 1 - i)
+          if (i < nr) {
+            const double u = (double)q[p] - c;
+            double pw[N];
+            pw[0] = u;
+#pragma unroll
+            for (int k = 1; k < N; ++k) pw[k] = pw[k - 1] * u;
+            // output row rr takes tap i - rr (a zero weight outside [0, 2R])
+#pragma unroll
+            for (int rr = 0; rr < kTY; ++rr) {
+              const double wv = wts[i - rr];
+#pragma unroll
+              for (int k = 0; k < N; ++k) acc[rr][k] = fma(wv, pw[k], acc[rr][k]);
+            }
+            if (BOUNDS && first) {
+              const float v = q[p] + 0.0f;     // -0 -> +0, as the bounds kernel
+              if (i >= kTY - 1 && i <= 2 * R) {
+                cmn = fminf(cmn, v);
+                cmx = fmaxf(cmx, v);
+              } else {
+#pragma unroll
+                for (int rr = 0; rr < kTY; ++rr)
+                  if (i >= rr && i <= rr + 2 * R) {
+                    mn[rr] = fminf(mn[rr], v);
+                    mx[rr] = fmaxf(mx[rr], v);
+                  }
+              }
+            }
+          }
+        }
+      }
+      if constexpr (SW) {
+        // Row rr's sums are the top half's slot rr plus the bottom half's
+        // slot kTY-1-rr. The top lane finishes rows 0 .. kTY/2-1 and its
+        // partner (lane + 32) rows kTY/2 .. kTY-1, each receiving the slot it
+        // lacks from the other in one exchange per row and power.
+        constexpr int kH = kWave / 2;
+        float cn = 0.f, cx = 0.f;
+        if (BOUNDS && first) {
+          cn = fminf(cmn, __shfl_xor(cmn, kH));
+          cx = fmaxf(cmx, __shfl_xor(cmx, kH));
+        }
+#pragma unroll
+        for (int q = 0; q < kTY / 2; ++q) {
+          const int row = rev ? kTY / 2 + q : q;
+#pragma unroll
+          for (int k = 0; k < N; ++k) {
+            const double snd = rev ? acc[kTY - 1 - q][k] : acc[kTY / 2 + q][k];
+            const double own = rev ? acc[kTY / 2 - 1 - q][k] : acc[q][k];
+            vsum[(k * kTY + row) * ES + tc] = own + __shfl_xor(snd, kH);
+          }
+          if (BOUNDS && first) {
+            const float sn = rev ? mn[kTY - 1 - q] : mn[kTY / 2 + q];
+            const float sx = rev ? mx[kTY - 1 - q] : mx[kTY / 2 + q];
+            const float on = rev ? mn[kTY / 2 - 1 - q] : mn[q];
+            const float ox = rev ? mx[kTY / 2 - 1 - q] : mx[q];
+            vmm[row * ES + tc] = make_float2(fminf(fminf(on, __shfl_xor(sn, kH)), cn),
+                                             fmaxf(fmaxf(ox, __shfl_xor(sx, kH)), cx));
+          }
+        }
+      } else {
+#pragma unroll
+        for (int rr = 0; rr < kTY; ++rr)
+#pragma unroll
+          for (int k = 0; k < N; ++k) vsum[(k * kTY + rr) * ES + tc] = acc[rr][k];
+        if (BOUNDS && first) {
+#pragma unroll
+          for (int rr = 0; rr < kTY; ++rr)
+            vmm[rr * ES + tc] = make_float2(fminf(mn[rr], cmn), fmaxf(mx[rr], cmx));
+        }
+      }
+    };
+    if (sw) {
+      if constexpr (kSplit) {
+        if (col_ok) vertical(std::true_type{});
+      }
+    } else if (col_ok) {
+      if (!first) load_chunk(std::false_type{}, 0, qn);
       double acc[kTY][N];
 #pragma unroll
       for (int rr = 0; rr < kTY; ++rr)
@@ -642,7 +780,7 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
         float q[kPF];
 #pragma unroll
         for (int p = 0; p < kPF; ++p) q[p] = qn[p];
-        if (i0 + kPF < n_in) load_chunk(i0 + kPF, qn);
+        if (i0 + kPF < n_in) load_chunk(std::false_type{}, i0 + kPF, qn);
 #pragma unroll
         for (int p = 0; p < kPF; ++p) {
           const int i = i0 + p;
