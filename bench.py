@@ -135,8 +135,11 @@ def measured_traffic(workload: str, stage: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=200)
+    # (5000 steps of the default workload time about a quarter of a second;
+    # with 1000 the two-stream rate moved by 4-5% from run to run and read
+    # 3% low, the two streams' pipeline taking a while to settle)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--streams", type=int, default=N_STREAMS,
                     help="streams the timed steps alternate between (1 for profiling: "

@@ -125,7 +125,10 @@ def test_range_stage_on_oracle_stack(torch, abf, precision):
 
 
 # ----------------------------------------------------------------- end to end
-SMALL = [("box", 3, 5), ("box", 1, 0), ("box", 2, 1), ("box", 5, 8), ("gaussian", 4, 6), ("gaussian", 9, 3)]
+# (Gaussian R = 1 and 16: the tile kernel's split tail wave with its shortest
+# halves, 3 rows, and its widest tail, 32 columns)
+SMALL = [("box", 3, 5), ("box", 1, 0), ("box", 2, 1), ("box", 5, 8), ("gaussian", 4, 6), ("gaussian", 9, 3),
+         ("gaussian", 1, 4), ("gaussian", 16, 5)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -262,7 +265,8 @@ def test_stack_reuse_for_new_theta_sigma(torch, abf):
 
 SINGLE_PASS = [((256, 300), 15, 6), ((37, 300), 5, 8), ((300, 37), 20, 5), ((1, 129), 4, 6),
                ((129, 1), 4, 6), ((5, 7), 20, 3), ((1, 1), 3, 2), ((70, 90), 0, 6), ((70, 90), 1, 7),
-               ((130, 517), 2, 1), ((150, 700), 12, 8), ((120, 400), 40, 7), ((90, 260), 60, 8)]
+               ((130, 517), 2, 1), ((150, 700), 12, 8), ((120, 400), 40, 7), ((90, 260), 60, 8),
+               ((64, 390), 16, 6)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
