@@ -30,8 +30,9 @@
 // columns, so alpha/beta loads and moment stores are coalesced.
 //
 // Gaussian kernel: a 2-D tile with register-blocked separable weighted sums
-// (O(R) per pixel); for radii too large for its LDS tile, the strip layout
-// of the box kernel with direct weighted sums.
+// (O(R) per pixel), at least 64 output columns wide for every radius up to
+// ABF_RHO_MAX. With unit weights it also serves the FP64 box path at
+// N >= 7, where the box kernel's running sums are not accurate enough.
 #include "abf_internal.h"
 #include "range_eval.h"
 
