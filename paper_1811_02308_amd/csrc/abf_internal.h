@@ -12,6 +12,22 @@ constexpr int kNMax = 8;
 constexpr int kRhoMax = 96;
 constexpr int kWave = 64;
 
+// Minimum and maximum of two finite floats in one instruction each: the
+// median of (a, b, -inf) and of (a, b, +inf). fminf and fmaxf must also
+// quiet signalling NaNs, which costs two more instructions per call on
+// values loaded from memory. The kernels' inputs are finite (a documented
+// precondition) and carry no -0 (they add +0.0f on load), so both forms
+// give the same bits. A kernel makes one FinMinMax at its start: the two
+// infinities pass once through an empty asm statement (no instruction;
+// they stay in scalar registers), so that the optimizer neither turns the
+// median back into fminf / fmaxf nor rebuilds the constants at every use.
+struct FinMinMax {
+  float lo, hi;
+  __device__ FinMinMax() : lo(-INFINITY), hi(INFINITY) { asm("" : "+s"(lo), "+s"(hi)); }
+  __device__ float min(float a, float b) const { return __builtin_amdgcn_fmed3f(a, b, lo); }
+  __device__ float max(float a, float b) const { return __builtin_amdgcn_fmed3f(a, b, hi); }
+};
+
 // Gauss-Legendre rules on [0, 1] used by the range kernel: 16 nodes for the
 // FP64 path, 12 for the mixed path.
 constexpr int kGLNodes = 16;

@@ -27,6 +27,7 @@ __global__ __launch_bounds__(kThreads) void vh_rows(
     const void* __restrict__ in, long long in_pitch, int rows, int cols, int R, int ROWS,
     float2* __restrict__ out_t, long long out_pitch,   // FIRST: transposed float2
     float* __restrict__ out_a, float* __restrict__ out_b, long long ab_pitch) {
+  const FinMinMax fm;
   extern __shared__ float2 smem[];
   const int E = kTX + 2 * R;
   float2* ext = smem;                 // ROWS x E
@@ -60,8 +61,8 @@ __global__ __launch_bounds__(kThreads) void vh_rows(
     const float2* er = ext + r * E;
     for (int e = e_end - 1; e >= s; --e) {
       const float2 v = er[e];
-      mn = fminf(mn, v.x);
-      mx = fmaxf(mx, v.y);
+      mn = fm.min(mn, v.x);
+      mx = fm.max(mx, v.y);
       if (e < kTX) res[r * kTX + e] = make_float2(mn, mx);
     }
   }
@@ -76,12 +77,12 @@ __global__ __launch_bounds__(kThreads) void vh_rows(
     const float2* er = ext + r * E;
     for (int e = s; e < e_end; ++e) {
       const float2 v = er[e];
-      mn = fminf(mn, v.x);
-      mx = fmaxf(mx, v.y);
+      mn = fm.min(mn, v.x);
+      mx = fm.max(mx, v.y);
       if (e >= 2 * R) {
         float2* o = res + r * kTX + (e - 2 * R);
         const float2 p = *o;
-        *o = make_float2(fminf(p.x, mn), fmaxf(p.y, mx));
+        *o = make_float2(fm.min(p.x, mn), fm.max(p.y, mx));
       }
     }
   }
@@ -118,7 +119,8 @@ constexpr int kHItems = 3;
 static_assert((kMTY + 2 * kTileRMax) * (kMTX / 8) <= kHItems * kThreads, "horizontal items per thread");
 
 template <typename Get>
-__device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&mx)[8]) {
+__device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&mx)[8],
+                                       const FinMinMax& fm) {
   // windows [v, v + 2R] of the sequence get(0 .. 7 + 2R). For 2R >= 6 each
   // window is [v, 6] + [7, 2R] (the shared core, empty at 2R = 6) +
   // [2R + 1, 2R + v]; smaller windows are taken directly.
@@ -128,8 +130,8 @@ __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&m
       float lo = INFINITY, hi = -INFINITY;
       for (int i = 0; i <= 2 * R; ++i) {
         const float2 q = get(v + i);
-        lo = fminf(lo, q.x);
-        hi = fmaxf(hi, q.y);
+        lo = fm.min(lo, q.x);
+        hi = fm.max(hi, q.y);
       }
       mn[v] = lo;
       mx[v] = hi;
@@ -139,16 +141,16 @@ __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&m
   float clo = INFINITY, chi = -INFINITY;
   for (int i = 7; i <= 2 * R; ++i) {
     const float2 q = get(i);
-    clo = fminf(clo, q.x);
-    chi = fmaxf(chi, q.y);
+    clo = fm.min(clo, q.x);
+    chi = fm.max(chi, q.y);
   }
   // suffixes over [v, 6], v = 6 .. 0
   float slo = clo, shi = chi;
 #pragma unroll
   for (int v = 6; v >= 0; --v) {
     const float2 q = get(v);
-    slo = fminf(slo, q.x);
-    shi = fmaxf(shi, q.y);
+    slo = fm.min(slo, q.x);
+    shi = fm.max(shi, q.y);
     mn[v] = slo;
     mx[v] = shi;
   }
@@ -159,16 +161,17 @@ __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&m
 #pragma unroll
   for (int v = 1; v < 8; ++v) {
     const float2 q = get(2 * R + v);
-    plo = fminf(plo, q.x);
-    phi = fmaxf(phi, q.y);
-    mn[v] = fminf(mn[v], plo);
-    mx[v] = fmaxf(mx[v], phi);
+    plo = fm.min(plo, q.x);
+    phi = fm.max(phi, q.y);
+    mn[v] = fm.min(mn[v], plo);
+    mx[v] = fm.max(mx[v], phi);
   }
 }
 
 __global__ __launch_bounds__(kThreads) void minmax_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     float* __restrict__ out_a, float* __restrict__ out_b, long long op, Batch bt) {
+  const FinMinMax fm;
   extern __shared__ float lds[];
   img += blockIdx.z * bt.img;
   out_a = byte_offset(out_a, blockIdx.z * bt.stack);
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void minmax_tile(
     if (it < n_items) {
       const int r = it % EY, g = it / EY;
       const float* row = tile + r * XS + 8 * g;
-      slide8([&](int i) { const float v = row[i]; return make_float2(v, v); }, R, hmn[q], hmx[q]);
+      slide8([&](int i) { const float v = row[i]; return make_float2(v, v); }, R, hmn[q], hmx[q], fm);
     }
   }
   __syncthreads();
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void minmax_tile(
     const int c = it % kMTX, g = it / kMTX;
     const float2* col = hres + (8 * g) * kHS + c;
     float mn[8], mx[8];
-    slide8([&](int i) { return col[i * kHS]; }, R, mn, mx);
+    slide8([&](int i) { return col[i * kHS]; }, R, mn, mx, fm);
     const int x = x0 + c;
     if (x < W) {
 #pragma unroll

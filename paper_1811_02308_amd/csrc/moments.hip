@@ -531,6 +531,7 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   // bounds taken here as well the kernel was measured slower than the two
   // kernels of the stack path)
   static_assert(!(FUSED && BOUNDS), "the fused range stage reads the bounds from the stack");
+  const FinMinMax fm;      // (window bounds)
   // dynamic LDS: [N][kTY][ES] doubles (vertical sums), the tap weights
   // (tile_wext_len(R) doubles), then (BOUNDS) [kTY][ES] float2 (min, max);
   // 16-byte aligned for the pair reads of phase 2
@@ -703,14 +704,14 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
             if (BOUNDS && first) {
               const float v = q[p] + 0.0f;     // -0 -> +0, as the bounds kernel
               if (i >= kTY - 1 && i <= 2 * R) {
-                cmn = fminf(cmn, v);
-                cmx = fmaxf(cmx, v);
+                cmn = fm.min(cmn, v);
+                cmx = fm.max(cmx, v);
               } else {
 #pragma unroll
                 for (int rr = 0; rr < kTY; ++rr)
                   if (i >= rr && i <= rr + 2 * R) {
-                    mn[rr] = fminf(mn[rr], v);
-                    mx[rr] = fmaxf(mx[rr], v);
+                    mn[rr] = fm.min(mn[rr], v);
+                    mx[rr] = fm.max(mx[rr], v);
                   }
               }
             }
@@ -725,8 +726,8 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
         constexpr int kH = kWave / 2;
         float cn = 0.f, cx = 0.f;
         if (BOUNDS && first) {
-          cn = fminf(cmn, __shfl_xor(cmn, kH));
-          cx = fmaxf(cmx, __shfl_xor(cmx, kH));
+          cn = fm.min(cmn, __shfl_xor(cmn, kH));
+          cx = fm.max(cmx, __shfl_xor(cmx, kH));
         }
 #pragma unroll
         for (int q = 0; q < kTY / 2; ++q) {
@@ -742,8 +743,8 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
             const float sx = rev ? mx[kTY - 1 - q] : mx[kTY / 2 + q];
             const float on = rev ? mn[kTY / 2 - 1 - q] : mn[q];
             const float ox = rev ? mx[kTY / 2 - 1 - q] : mx[q];
-            vmm[row * ES + tc] = make_float2(fminf(fminf(on, __shfl_xor(sn, kH)), cn),
-                                             fmaxf(fmaxf(ox, __shfl_xor(sx, kH)), cx));
+            vmm[row * ES + tc] = make_float2(fm.min(fm.min(on, __shfl_xor(sn, kH)), cn),
+                                             fm.max(fm.max(ox, __shfl_xor(sx, kH)), cx));
           }
         }
       } else {
@@ -754,7 +755,7 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
         if (BOUNDS && first) {
 #pragma unroll
           for (int rr = 0; rr < kTY; ++rr)
-            vmm[rr * ES + tc] = make_float2(fminf(mn[rr], cmn), fmaxf(mx[rr], cmx));
+            vmm[rr * ES + tc] = make_float2(fm.min(mn[rr], cmn), fm.max(mx[rr], cmx));
         }
       }
     };
@@ -801,14 +802,14 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
             if (BOUNDS && first) {
               const float v = q[p] + 0.0f;     // -0 -> +0, as the bounds kernel
               if (i >= kTY - 1 && i <= 2 * R) {
-                cmn = fminf(cmn, v);
-                cmx = fmaxf(cmx, v);
+                cmn = fm.min(cmn, v);
+                cmx = fm.max(cmx, v);
               } else {
 #pragma unroll
                 for (int rr = 0; rr < kTY; ++rr)
                   if (i >= rr && i <= rr + 2 * R) {
-                    mn[rr] = fminf(mn[rr], v);
-                    mx[rr] = fmaxf(mx[rr], v);
+                    mn[rr] = fm.min(mn[rr], v);
+                    mx[rr] = fm.max(mx[rr], v);
                   }
               }
             }
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
       if (BOUNDS && first) {
 #pragma unroll
         for (int rr = 0; rr < kTY; ++rr)
-          vmm[rr * ES + tc] = make_float2(fminf(mn[rr], cmn), fmaxf(mx[rr], cmx));
+          vmm[rr * ES + tc] = make_float2(fm.min(mn[rr], cmn), fm.max(mx[rr], cmx));
       }
     }
     __syncthreads();
@@ -851,14 +852,14 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
       const float4* vm4 = reinterpret_cast<const float4*>(vmm);
       auto take = [&](int cc, float lo, float hi) {
         if (cc >= kCB - 1 && cc <= 2 * R) {
-          hmn = fminf(hmn, lo);
-          hmx = fmaxf(hmx, hi);
+          hmn = fm.min(hmn, lo);
+          hmx = fm.max(hmx, hi);
         } else {
 #pragma unroll
           for (int v = 0; v < kCB; ++v)
             if (cc >= v && cc <= v + 2 * R) {
-              bmn[v] = fminf(bmn[v], lo);
-              bmx[v] = fmaxf(bmx[v], hi);
+              bmn[v] = fm.min(bmn[v], lo);
+              bmx[v] = fm.max(bmx[v], hi);
             }
         }
       };
@@ -893,8 +894,8 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
           if (y < H && x < W && xl + v < TX) {
             const long long idx = (long long)y * sp + x;
             if (BOUNDS) {
-              pa[v] = fminf(bmn[v], hmn);
-              pb[v] = fmaxf(bmx[v], hmx);
+              pa[v] = fm.min(bmn[v], hmn);
+              pb[v] = fm.max(bmx[v], hmx);
               alpha[idx] = pa[v];
               beta[idx] = pb[v];
             } else {
