@@ -97,7 +97,7 @@ __device__ __forceinline__ bool legendre_from_moments(double (&m)[N + 1], float 
   }
   const double mid = 0.5 * ((double)a + (double)b) - c;
   const double half = 0.5 * ((double)b - (double)a);
-  const double ih = 1.0 / half;
+  const double ih = rcp(half);      // (a few ulp; a scale, not an exact quantity)
   // The shift below amplifies the rounding of m_r by about
   // rho^k, rho = (|mid| + half) / half.
   const double rho = fma(fabs(mid), ih, 1.0);
