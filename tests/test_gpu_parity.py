@@ -298,25 +298,26 @@ def test_single_pass_stack_equals_two_pass(torch, abf, precision, shape, R, N):
     assert np.array_equal(p1[1].cpu().numpy().view(np.uint32), hi.astype(np.float32).view(np.uint32))
 
 
-@pytest.mark.parametrize("kernel,R", [("box", 3), ("gaussian", 7)])
-def test_fp64_every_pixel_high_contrast_n8(torch, abf, kernel, R):
-    """FP64 path at N = 8 on clipped, high-contrast content (Voronoi cells at
+@pytest.mark.parametrize("kernel,R,N", [("box", 3, 8), ("gaussian", 7, 8), ("box", 5, 7),
+                                        ("gaussian", 12, 7)])
+def test_fp64_every_pixel_high_contrast(torch, abf, kernel, R, N):
+    """FP64 path at N = 7, 8 on clipped, high-contrast content (Voronoi cells at
     levels U[0, 255] plus noise, clipped): every pixel within 1e-6 of the
     oracle. Strips and tiles there span dark and bright cells, so one origin
     for a region's power sums is far from many windows, and the box
     kernel's running sums carry the rounding of the strip's extreme values;
     with a single origin and the N <= 5 threshold at every degree, the FP64
     path missed the bound on 13 (box) and 239 (Gaussian) pixels of this
-    image."""
+    image at N = 8."""
     from synth.generators import block_constant
     h, w = 256, 512
     f = voronoi(1201, h, w, n_seed=24, noise=15.0)
     sg = block_constant(np.random.default_rng(1202), h, w, 10, 40)
     ss = R / 3.0 if kernel == "gaussian" else 0.0
-    out = abf.fast(dev(torch, f), dev(torch, sg), kernel=kernel, rho=R, N=8, sigma_s=ss,
+    out = abf.fast(dev(torch, f), dev(torch, sg), kernel=kernel, rho=R, N=N, sigma_s=ss,
                    precision="fp64")
     torch.cuda.synchronize()
-    ref = oracle.fast_abf(f, None, sg, kernel, R, 8, sigma_s=ss)
+    ref = oracle.fast_abf(f, None, sg, kernel, R, N, sigma_s=ss)
     err = np.abs(out.cpu().numpy() - ref)
     assert err.max() <= TOL["fp64"], (float(err.max()), int((err > TOL["fp64"]).sum()))
 
