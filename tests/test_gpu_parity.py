@@ -76,6 +76,36 @@ def test_minmax_voronoi_full(torch, abf):
         assert np.array_equal(a.cpu().numpy(), lo) and np.array_equal(b.cpu().numpy(), hi)
 
 
+
+@pytest.mark.parametrize("R", [2, 5, 15, 30])
+def test_bounds_mixed_sign_bit_exact(torch, abf, R):
+    """Window bounds of finite inputs of both signs, with -0, +0, subnormal
+    and near-FP32-max magnitudes (the kernels take each min/max as the
+    median against an infinity): minmax_tile bit for bit, and the Gaussian
+    tile kernel's own bounds (on values of moderate size, whose power sums
+    stay finite) bit for bit where it takes them."""
+    rng = np.random.default_rng(4321 + R)
+    h, w = 97, 301
+    f = (rng.standard_normal((h, w)) * 1e3).astype(np.float32)
+    f[rng.random((h, w)) < 0.05] = np.float32(-0.0)
+    f[rng.random((h, w)) < 0.02] = np.float32(1e-40)
+    f[rng.random((h, w)) < 0.02] = np.float32(-1e-40)
+    big = f.copy()
+    big[rng.random((h, w)) < 0.02] = np.float32(3.0e38)
+    big[rng.random((h, w)) < 0.02] = np.float32(-3.0e38)
+    a, b = abf.minmax(dev(torch, big), R)
+    torch.cuda.synchronize()
+    lo, hi = window_minmax(big, R)
+    assert np.array_equal(a.cpu().numpy().view(np.uint32), lo.view(np.uint32))
+    assert np.array_equal(b.cpu().numpy().view(np.uint32), hi.view(np.uint32))
+    if abf.stack_single_pass(h, w, "gaussian", R, 4):
+        st = abf.moment_stack(dev(torch, f), kernel="gaussian", rho=R, N=4, precision="mixed")
+        torch.cuda.synchronize()
+        pl = abf.stack_planes(st, h, w, 4, "mixed")
+        lo, hi = window_minmax(f, R)
+        assert np.array_equal(pl[0].cpu().numpy().view(np.uint32), lo.view(np.uint32))
+        assert np.array_equal(pl[1].cpu().numpy().view(np.uint32), hi.view(np.uint32))
+
 # ----------------------------------------------------------------- stack
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("kernel,R,N", [("box", 3, 5), ("box", 20, 8), ("gaussian", 6, 6)])
