@@ -131,6 +131,26 @@ abf_status abf_moment_stack(const float* img, int h, int w, long long pitch,
 int abf_stack_single_pass(int h, int w, int kernel_kind, int rho, int N);
 
 /*
+ * abf_stack_kernel -- which moment kernel abf_moment_stack (and so abf_fast,
+ * abf_fast_strided, abf_fast_batched) runs for an h x w image with this
+ * kernel, rho, N and precision: the step of Algorithm 1 that forms the
+ * local-histogram moments by convolution (Prop. 2) and shifts them to
+ * [alpha_i, beta_i] (Prop. 3). Values:
+ *   ABF_STACK_BOUNDS_ONLY  N = 0: no moment planes, window bounds only
+ *   ABF_STACK_BOX          box kernel, running sums (O(1) per pixel in rho)
+ *   ABF_STACK_TILE         2-D tile kernel, direct separable sums (Gaussian
+ *                          weights, or unit weights for the FP64 box path
+ *                          at N >= 7), LDS row stride 160 (tile + 2 rho fit)
+ *   ABF_STACK_TILE_WIDE    the same kernel with LDS row stride 256
+ *   ABF_STACK_MFMA         Gaussian sums as banded FP64 matrix products
+ * Returns -1 for invalid arguments. Host only; lets callers and tests
+ * confirm which kernel a configuration exercises.
+ */
+enum { ABF_STACK_BOUNDS_ONLY = 0, ABF_STACK_BOX = 1, ABF_STACK_TILE = 2,
+       ABF_STACK_TILE_WIDE = 3, ABF_STACK_MFMA = 4 };
+int abf_stack_kernel(int h, int w, int kernel_kind, int rho, int N, int precision);
+
+/*
  * abf_stack_moments -- the second half of abf_moment_stack: given a stack
  * whose planes 0 and 1 already hold alpha_i and beta_i for this image and
  * rho (e.g. written by abf_minmax with out_pitch = abf_stack_pitch(w)),

@@ -21,7 +21,7 @@ __all__ = [
     "range_from_stack", "fast_batched", "minmax_into_stack", "stack_moments",
     "fast_strided", "sigma_local_std", "moments_range", "uniform_prior", "range_uniform_from_stack",
     "sharpen_maps", "mrtv_sigma", "grey", "texture_filter_paper", "workspace_bytes", "stack_bytes",
-    "stack_planes", "Request", "KERNELS", "PRECISIONS", "ABFError",
+    "stack_planes", "stack_kernel", "Request", "KERNELS", "PRECISIONS", "ABFError",
 ]
 
 KERNELS = {"box": 0, "gaussian": 1}
@@ -75,6 +75,7 @@ def lib():
         "abf_minmax": ([vp, i, i, ll, i, vp, vp, ll, vp, sz, vp], i),
         "abf_moment_stack": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp, sz, vp], i),
         "abf_stack_single_pass": ([i, i, i, i, i], i),
+        "abf_stack_kernel": ([i, i, i, i, i, i], i),
         "abf_stack_moments": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp], i),
         "abf_range": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
         "abf_moments_range": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, sz, vp, ll, vp], i),
@@ -116,6 +117,19 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Context in which the binding allocates outputs and temporaries: the
+    stream the call's kernels run on. Torch's caching allocator ties a block
+    to the stream current at allocation, and only reuses it for work ordered
+    after that stream's pending kernels; a workspace dropped at return while
+    the kernels still run on another stream could otherwise be handed out
+    again on the current stream and overwritten mid-flight."""
+    import contextlib
+    if stream is None:
+        return contextlib.nullcontext()
+    return _torch().cuda.stream(stream)
+
+
 def _plane(t, name):
     torch = _torch()
     if t is None:
@@ -151,10 +165,23 @@ def _common_pitch(img, *others):
     return p
 
 
-def _alloc_bytes(nbytes, device):
+def _alloc_bytes(nbytes, device, stream=None):
     torch = _torch()
     # torch's caching allocator returns blocks aligned to at least 512 bytes
-    return torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=device)
+    with _on(stream):
+        return torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=device)
+
+
+def _empty(shape, dtype, device, stream=None):
+    """torch.empty on the stream the call's kernels run on (see _on)."""
+    torch = _torch()
+    with _on(stream):
+        return torch.empty(shape, dtype=dtype, device=device)
+
+
+def _out_dtype(p):
+    torch = _torch()
+    return torch.float64 if p == 0 else torch.float32
 
 
 def workspace_bytes(h, w, rho, N, precision="mixed"):
@@ -175,10 +202,10 @@ def fast(img, sigma, theta=None, kernel="box", rho=3, N=5, sigma_s=0.0, precisio
     pitch = _common_pitch(img, sigma, theta)
     p = _prec(precision)
     if out is None:
-        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+        out = _empty((h, w), _out_dtype(p), img.device, stream)
     need = lib().abf_workspace_bytes(h, w, rho, N, p)
     if workspace is None:
-        workspace = _alloc_bytes(need, img.device)
+        workspace = _alloc_bytes(need, img.device, stream)
     st = lib().abf_fast(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
                         float(sigma_s), int(rho), int(N), p, FLAG_CLAMP if clamp else 0,
                         _ptr(out), out.stride(0), _ptr(workspace), workspace.numel(), _stream(stream))
@@ -195,7 +222,7 @@ def bruteforce(img, sigma, theta=None, kernel="box", rho=3, sigma_s=0.0, precisi
     pitch = _common_pitch(img, sigma, theta)
     p = _prec(precision)
     if out is None:
-        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+        out = _empty((h, w), _out_dtype(p), img.device, stream)
     st = lib().abf_bruteforce(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
                               float(sigma_s), int(rho), p, _ptr(out), out.stride(0), _stream(stream))
     _check(st, "abf_bruteforce")
@@ -207,9 +234,9 @@ def minmax(img, rho, stream=None):
     torch = _torch()
     img = _plane(img, "img")
     h, w = img.shape
-    a = torch.empty((h, w), dtype=torch.float32, device=img.device)
-    b = torch.empty_like(a)
-    ws = _alloc_bytes(lib().abf_scratch_bytes(h, w, rho), img.device)
+    a = _empty((h, w), torch.float32, img.device, stream)
+    b = _empty((h, w), torch.float32, img.device, stream)
+    ws = _alloc_bytes(lib().abf_scratch_bytes(h, w, rho), img.device, stream)
     st = lib().abf_minmax(_ptr(img), h, w, img.stride(0), int(rho), _ptr(a), _ptr(b), a.stride(0),
                           _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "abf_minmax")
@@ -223,9 +250,9 @@ def moment_stack(img, kernel="box", rho=3, N=5, sigma_s=0.0, precision="mixed", 
     h, w = img.shape
     p = _prec(precision)
     if stack is None:
-        stack = _alloc_bytes(lib().abf_stack_bytes(h, w, N, p), img.device)
+        stack = _alloc_bytes(lib().abf_stack_bytes(h, w, N, p), img.device, stream)
     if workspace is None:
-        workspace = _alloc_bytes(lib().abf_scratch_bytes(h, w, rho), img.device)
+        workspace = _alloc_bytes(lib().abf_scratch_bytes(h, w, rho), img.device, stream)
     st = lib().abf_moment_stack(_ptr(img), h, w, img.stride(0), _kind(kernel), float(sigma_s),
                                 int(rho), int(N), p, _ptr(stack), stack.numel(), _ptr(workspace),
                                 workspace.numel(), _stream(stream))
@@ -239,6 +266,19 @@ def stack_single_pass(h, w, kernel="box", rho=3, N=5):
     return bool(lib().abf_stack_single_pass(int(h), int(w), _kind(kernel), int(rho), int(N)))
 
 
+STACK_KERNELS = {0: "bounds_only", 1: "box", 2: "tile", 3: "tile_wide", 4: "mfma"}
+
+
+def stack_kernel(h, w, kernel="box", rho=3, N=5, precision="mixed"):
+    """abf_stack_kernel: name of the moment kernel that builds the stack of an
+    h x w image with these parameters ('box', 'tile', 'tile_wide', 'mfma',
+    'bounds_only' for N = 0)."""
+    k = int(lib().abf_stack_kernel(int(h), int(w), _kind(kernel), int(rho), int(N), _prec(precision)))
+    if k < 0:
+        raise ABFError("abf_stack_kernel: invalid arguments")
+    return STACK_KERNELS[k]
+
+
 def minmax_into_stack(img, stack, rho, N, precision="mixed", workspace=None, stream=None):
     """abf_minmax writing alpha/beta into planes 0 and 1 of a stack buffer."""
     img = _plane(img, "img")
@@ -248,7 +288,7 @@ def minmax_into_stack(img, stack, rho, N, precision="mixed", workspace=None, str
     if stack.numel() < L.abf_stack_bytes(h, w, N, p):
         raise ABFError("stack buffer too small")
     if workspace is None:
-        workspace = _alloc_bytes(L.abf_scratch_bytes(h, w, rho), img.device)
+        workspace = _alloc_bytes(L.abf_scratch_bytes(h, w, rho), img.device, stream)
     a = ctypes.c_void_p(stack.data_ptr())
     b = ctypes.c_void_p(stack.data_ptr() + int(L.abf_stack_plane_offset(h, w, N, p, 1)))
     st = L.abf_minmax(_ptr(img), h, w, img.stride(0), int(rho), a, b, L.abf_stack_pitch(w),
@@ -298,7 +338,7 @@ def range_from_stack(stack, sigma, img=None, theta=None, N=5, precision="mixed",
     pitch = _common_pitch(sigma, img, theta)
     p = _prec(precision)
     if out is None:
-        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=sigma.device)
+        out = _empty((h, w), _out_dtype(p), sigma.device, stream)
     st = lib().abf_range(_ptr(stack), stack.numel(), _ptr(img), _ptr(theta), _ptr(sigma), h, w,
                          pitch, int(N), p, FLAG_CLAMP if clamp else 0, _ptr(out), out.stride(0),
                          _stream(stream))
@@ -317,7 +357,7 @@ def moments_range(img, stack, sigma, theta=None, kernel="box", rho=3, N=5, sigma
     pitch = _common_pitch(img, sigma, theta)
     p = _prec(precision)
     if out is None:
-        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+        out = _empty((h, w), _out_dtype(p), img.device, stream)
     flags = (FLAG_CLAMP if clamp else 0) | (FLAG_KEEP_STACK if keep_stack else 0)
     st = lib().abf_moments_range(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
                                  float(sigma_s), int(rho), int(N), p, flags, _ptr(stack),
@@ -337,9 +377,9 @@ def uniform_prior(img, sigma, theta=None, kernel="box", rho=3, sigma_s=0.0, prec
     p = _prec(precision)
     L = lib()
     if out is None:
-        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+        out = _empty((h, w), _out_dtype(p), img.device, stream)
     if workspace is None:
-        workspace = _alloc_bytes(L.abf_workspace_bytes(h, w, int(rho), 1, p), img.device)
+        workspace = _alloc_bytes(L.abf_workspace_bytes(h, w, int(rho), 1, p), img.device, stream)
     st = L.abf_uniform_prior(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
                              float(sigma_s), int(rho), p, FLAG_CLAMP if clamp else 0, _ptr(out),
                              out.stride(0), _ptr(workspace), workspace.numel(), _stream(stream))
@@ -356,7 +396,7 @@ def range_uniform_from_stack(stack, img, sigma, theta=None, N=5, precision="mixe
     pitch = _common_pitch(img, sigma, theta)
     p = _prec(precision)
     if out is None:
-        out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+        out = _empty((h, w), _out_dtype(p), img.device, stream)
     st = lib().abf_range_uniform(_ptr(stack), stack.numel(), _ptr(img), _ptr(theta), _ptr(sigma),
                                  h, w, pitch, int(N), p, FLAG_CLAMP if clamp else 0, _ptr(out),
                                  out.stride(0), _stream(stream))
@@ -378,14 +418,14 @@ def fast_batched(items, precision="mixed", clamp=True, workspace=None, stream=No
         pitch = _common_pitch(img, sg, th)
         out = it.get("out")
         if out is None:
-            out = torch.empty((h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+            out = _empty((h, w), _out_dtype(p), img.device, stream)
         outs.append(out)
         reqs[i] = Request(img.data_ptr(), th.data_ptr() if th is not None else None, sg.data_ptr(),
                           h, w, pitch, _kind(it.get("kernel", "box")), float(it.get("sigma_s", 0.0)),
                           int(it["rho"]), int(it["N"]), out.data_ptr(), out.stride(0))
     need = lib().abf_batched_workspace_bytes(reqs, len(items), p)
     if workspace is None and items:
-        workspace = _alloc_bytes(need, items[0]["img"].device)
+        workspace = _alloc_bytes(need, items[0]["img"].device, stream)
     st = lib().abf_fast_batched(reqs, len(items), p, FLAG_CLAMP if clamp else 0,
                                 _ptr(workspace) if workspace is not None else None,
                                 workspace.numel() if workspace is not None else 0, _stream(stream))
@@ -419,10 +459,10 @@ def fast_strided(img, sigma, theta=None, kernel="box", rho=3, N=5, sigma_s=0.0,
             raise ABFError("theta/sigma must have the image batch's shape and strides")
     p = _prec(precision)
     if out is None:
-        out = torch.empty((n, h, w), dtype=torch.float64 if p == 0 else torch.float32, device=img.device)
+        out = _empty((n, h, w), _out_dtype(p), img.device, stream)
     need = lib().abf_strided_workspace_bytes(n, h, w, rho, N, p)
     if workspace is None:
-        workspace = _alloc_bytes(need, img.device)
+        workspace = _alloc_bytes(need, img.device, stream)
     st = lib().abf_fast_strided(_ptr(img), _ptr(theta), _ptr(sigma), n, h, w, img.stride(1),
                                 img.stride(0), _kind(kernel), float(sigma_s), int(rho), int(N), p,
                                 FLAG_CLAMP if clamp else 0, _ptr(out), out.stride(1), out.stride(0),
@@ -437,7 +477,7 @@ def sigma_local_std(img, radius=4, scale=3.0, lo=5.0, hi=80.0, out=None, stream=
     img = _batch3(img, "img")
     n, h, w = img.shape
     if out is None:
-        out = torch.empty((n, h, w), dtype=torch.float32, device=img.device)
+        out = _empty((n, h, w), torch.float32, img.device, stream)
     st = lib().abf_sigma_local_std(_ptr(img), n, h, w, img.stride(1), img.stride(0), int(radius),
                                    float(scale), float(lo), float(hi), _ptr(out), out.stride(1),
                                    out.stride(0), _stream(stream))
@@ -452,15 +492,20 @@ def texture_filter(frames, passes=3, rho=8, N=6, radius=4, scale=3.0, lo=5.0, hi
     repeatedly, channel by channel): each pass recomputes sigma from the
     current input's local contrast (abf_sigma_local_std) and filters the
     whole batch with one abf_fast_strided call (theta = f, box kernel).
-    Returns the output of the last pass (float32 for 'mixed')."""
+    Returns the output of the last pass (float32 for 'mixed'). Every torch
+    operation in between runs on ``stream`` as well."""
+    with _on(stream):
+        return _texture_filter(frames, passes, rho, N, radius, scale, lo, hi, precision, stream)
+
+
+def _texture_filter(frames, passes, rho, N, radius, scale, lo, hi, precision, stream):
     torch = _torch()
     x = _batch3(frames, "frames")
     n, h, w = x.shape
     p = _prec(precision)
-    ws = _alloc_bytes(lib().abf_strided_workspace_bytes(n, h, w, rho, N, p), x.device)
-    sig = torch.empty_like(x)
-    outs = [torch.empty((n, h, w), dtype=torch.float64 if p == 0 else torch.float32,
-                        device=x.device) for _ in range(2)]
+    ws = _alloc_bytes(lib().abf_strided_workspace_bytes(n, h, w, rho, N, p), x.device, stream)
+    sig = _empty(x.shape, torch.float32, x.device, stream)
+    outs = [_empty((n, h, w), _out_dtype(p), x.device, stream) for _ in range(2)]
     cur = x
     for i in range(passes):
         sigma_local_std(cur if cur.dtype == torch.float32 else cur.float(), radius, scale, lo, hi,
@@ -473,10 +518,10 @@ def texture_filter(frames, passes=3, rho=8, N=6, radius=4, scale=3.0, lo=5.0, hi
 
 
 # ---------------------------------------------------------------- application maps (Sec. IV)
-def _out3(t, n, h, w, like):
+def _out3(t, n, h, w, like, stream=None):
     torch = _torch()
     if t is None:
-        return torch.empty((n, h, w), dtype=torch.float32, device=like.device)
+        return _empty((n, h, w), torch.float32, like.device, stream)
     t = _batch3(t, "out")
     if tuple(t.shape) != (n, h, w):
         raise ABFError("output maps must have the input batch's shape")
@@ -489,8 +534,8 @@ def sharpen_maps(img, radius=5, log_sigma=1.0, lo=5.0, hi=40.0, v_ref=20.0, thet
     batch (n, h, w) or one image: theta = 2 f - fbar, sigma = affine(|LoG f|)."""
     x = _batch3(img, "img")
     n, h, w = x.shape
-    theta = _out3(theta, n, h, w, x)
-    sigma = _out3(sigma, n, h, w, x)
+    theta = _out3(theta, n, h, w, x, stream)
+    sigma = _out3(sigma, n, h, w, x, stream)
     if theta.stride() != sigma.stride():
         raise ABFError("theta and sigma outputs must share strides")
     st = lib().abf_sharpen_maps(_ptr(x), n, h, w, x.stride(1), x.stride(0), int(radius),
@@ -504,7 +549,7 @@ def mrtv_sigma(img, radius=2, eps=1e-3, lo=5.0, hi=80.0, v_ref=20.0, out=None, s
     """abf_mrtv_sigma: sigma = affine(mRTV) for a batch (n, h, w) or one image."""
     x = _batch3(img, "img")
     n, h, w = x.shape
-    out = _out3(out, n, h, w, x)
+    out = _out3(out, n, h, w, x, stream)
     st = lib().abf_mrtv_sigma(_ptr(x), n, h, w, x.stride(1), x.stride(0), int(radius), float(eps),
                               float(lo), float(hi), float(v_ref), _ptr(out), out.stride(1),
                               out.stride(0), _stream(stream))
@@ -523,7 +568,7 @@ def grey(rgb, out=None, stream=None):
     if rgb.dim() != 4 or rgb.shape[1] != 3 or rgb.stride(3) != 1:
         raise ABFError("rgb must be (n, 3, h, w) with unit column stride")
     n, _, h, w = rgb.shape
-    out = _out3(out, n, h, w, rgb)
+    out = _out3(out, n, h, w, rgb, stream)
     st = lib().abf_grey(_ptr(rgb), n, h, w, rgb.stride(2), rgb.stride(1), rgb.stride(0), _ptr(out),
                         out.stride(1), out.stride(0), _stream(stream))
     _check(st, "abf_grey")
@@ -542,7 +587,16 @@ def texture_filter_paper(frames, rho=8, N=6, mrtv_radius=2, eps=1e-3, lo=5.0, hi
               channel, sigma from |LoG| of its grey image (abf_sharpen_maps).
     The maps of all three channels of a frame are the grey image's (written
     once per channel plane). Returns pass 3's output (n, 3, h, w), or with
-    ``keep`` a dict of every intermediate."""
+    ``keep`` a dict of every intermediate. Every torch operation in between
+    (layout copies, dtype conversions) runs on ``stream`` as well."""
+    with _on(stream):
+        return _texture_filter_paper(frames, rho, N, mrtv_radius, eps, lo, hi, v_ref, shrink,
+                                     log_sigma, sharpen_lo, sharpen_hi, sharpen_v_ref, precision,
+                                     stream, keep)
+
+
+def _texture_filter_paper(frames, rho, N, mrtv_radius, eps, lo, hi, v_ref, shrink, log_sigma,
+                          sharpen_lo, sharpen_hi, sharpen_v_ref, precision, stream, keep):
     torch = _torch()
     if frames.dim() != 4 or frames.shape[1] != 3:
         raise ABFError("frames must be (n, 3, h, w)")
@@ -550,15 +604,15 @@ def texture_filter_paper(frames, rho=8, N=6, mrtv_radius=2, eps=1e-3, lo=5.0, hi
     x = frames.contiguous()
     planes = x.view(n * 3, h, w)
     p = _prec(precision)
-    ws = _alloc_bytes(lib().abf_strided_workspace_bytes(n * 3, h, w, rho, N, p), x.device)
-    sig3 = torch.empty((n, 3, h, w), dtype=torch.float32, device=x.device)
+    ws = _alloc_bytes(lib().abf_strided_workspace_bytes(n * 3, h, w, rho, N, p), x.device, stream)
+    sig3 = _empty((n, 3, h, w), torch.float32, x.device, stream)
     g0 = grey(x, stream=stream)
     for c in range(3):
         mrtv_sigma(g0, mrtv_radius, eps, lo, hi, v_ref, out=sig3[:, c], stream=stream)
     y1 = fast_strided(planes, sig3.view(n * 3, h, w), kernel="box", rho=rho, N=N,
                       precision=precision, workspace=ws, stream=stream)
     y1f = y1 if y1.dtype == torch.float32 else y1.float()
-    sig3b = torch.empty_like(sig3)
+    sig3b = _empty((n, 3, h, w), torch.float32, x.device, stream)
     for c in range(3):
         mrtv_sigma(g0, mrtv_radius, eps, shrink * lo, shrink * hi, v_ref, out=sig3b[:, c],
                    stream=stream)
@@ -568,7 +622,7 @@ def texture_filter_paper(frames, rho=8, N=6, mrtv_radius=2, eps=1e-3, lo=5.0, hi
     th, scratch = sharpen_maps(y2f, rho, log_sigma, sharpen_lo, sharpen_hi, sharpen_v_ref,
                                stream=stream)
     g2 = grey(y2f.view(n, 3, h, w), stream=stream)
-    sig3c = torch.empty_like(sig3)
+    sig3c = _empty((n, 3, h, w), torch.float32, x.device, stream)
     for c in range(3):
         sharpen_maps(g2, rho, log_sigma, sharpen_lo, sharpen_hi, sharpen_v_ref,
                      theta=scratch.view(n, 3, h, w)[:, c], sigma=sig3c[:, c], stream=stream)

@@ -126,6 +126,10 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           bool bounds = false);
 
 bool moments_fusable(int kernel_kind, int rho, int N, long long h, long long w);
+// Which moment kernel builds the stack (values of abf_stack_kernel); prec 0 =
+// FP64 stack, 1 = FP32; -1 if no kernel covers the arguments.
+enum { kStackBoundsOnly = 0, kStackBox = 1, kStackTile = 2, kStackTileWide = 3, kStackMfma = 4 };
+int stack_kernel_id(int kernel_kind, int rho, int N, int prec, long long h, long long w);
 bool moments_take_bounds(int kernel_kind, int rho, int N, long long h, long long w);
 
 hipError_t launch_range(const float* alpha, const float* beta, long long sp,

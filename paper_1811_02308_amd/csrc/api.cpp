@@ -206,6 +206,13 @@ int abf_stack_single_pass(int h, int w, int kernel_kind, int rho, int N) {
   return abf::moments_take_bounds(kernel_kind, rho, N, h, w) ? 1 : 0;
 }
 
+int abf_stack_kernel(int h, int w, int kernel_kind, int rho, int N, int precision) {
+  if (h < 1 || w < 1 || rho < 0 || rho > ABF_RHO_MAX || N < 0 || N > ABF_N_MAX ||
+      !kind_ok(kernel_kind) || !prec_ok(precision))
+    return -1;
+  return abf::stack_kernel_id(kernel_kind, rho, N, precision == ABF_PREC_FP64 ? 0 : 1, h, w);
+}
+
 abf_status abf_range(const void* stack, size_t stack_bytes, const float* img, const float* theta,
                      const float* sigma, int h, int w, long long pitch, int N, int precision,
                      unsigned flags, void* out, long long out_pitch, void* stream) {

@@ -1336,6 +1336,17 @@ bool moments_take_bounds(int kernel_kind, int rho, int N, long long h, long long
   return tx > 0 && ((N + 1) * kTY * es + tile_wext_len(rho)) * 8 + 64 <= 81920;
 }
 
+int stack_kernel_id(int kernel_kind, int rho, int N, int prec, long long h, long long w) {
+  if (N < 1) return kStackBoundsOnly;
+  // the FP64 box path at N >= 7 takes the tile kernel with unit weights
+  const bool box_tile = kernel_kind == 0 && prec == 0 && N >= 7;
+  if (kernel_kind == 0 && !box_tile) return kStackBox;
+  if (!box_tile && gauss_on_mfma(rho, N, h, w)) return kStackMfma;
+  const int tx = gauss_tile_tx(rho, N);
+  if (tx <= 0) return -1;
+  return tx + 2 * rho <= kESNarrow ? kStackTile : kStackTileWide;
+}
+
 bool moments_fusable(int kernel_kind, int rho, int N, long long h, long long w) {
   // The fused variant has no matrix-core form; where abf_stack_moments uses
   // the matrix-core kernel the fused call takes the stack path, so that its

@@ -265,7 +265,7 @@ class FakeExecutor:
 
     def footprint(self, r):
         px = r.pixels
-        return 4 * px * (1 + (r.theta is not None)), 4 * px * (r.N + 2), 8 * px
+        return 4 * px, 4 * px * (r.N + 2), 8 * px + 4 * px * (r.theta is not None)
 
     def launch(self, r, img_handle, stack_handle, t_admit):
         if r.id in self.fail_ids:
@@ -298,9 +298,15 @@ class GPUExecutor:
     """Runs requests on the MI355X through the HIP library, one torch (HIP)
     stream per slot, default priority. Inputs are staged through pinned host
     memory; the result is copied back into pinned memory on the same stream
-    and an event marks completion."""
+    and an event marks completion.
 
-    def __init__(self, n_slots=4, precision="mixed", device=0):
+    Resident images and stacks are produced on one slot's stream and may be
+    used by a request on another slot before that work has finished: every
+    cached handle carries the event recorded after its producer's work, and
+    a consumer's stream waits for it before using the handle. Theta is
+    per request (it is not part of the cached image)."""
+
+    def __init__(self, n_slots=4, precision="mixed", device=0, pinned_cap_bytes=2 << 30):
         import torch
         import paper_1811_02308_amd as abf
         self.torch, self.abf = torch, abf
@@ -309,24 +315,41 @@ class GPUExecutor:
         self.dev = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
         self.free_slots = list(range(n_slots))
-        self._pinned = {}          # id(host array) -> pinned copy (arrays reused across requests)
+        # pinned staging copies of host arrays reused across requests, LRU by
+        # bytes (a dropped copy stays valid for copies already enqueued: torch's
+        # pinned allocator keeps the block until they have run)
+        self._pinned = collections.OrderedDict()   # id(host array) -> (pinned, array)
+        self._pinned_bytes = 0
+        self.pinned_cap = int(pinned_cap_bytes)
         abf.lib()
 
     def _pin(self, a):
-        t = self._pinned.get(id(a))
-        if t is None or t[1] is not a:
-            t = (self.torch.from_numpy(a).pin_memory(), a)
-            self._pinned[id(a)] = t
-        return t[0]
+        key = id(a)
+        t = self._pinned.get(key)
+        if t is not None and t[1] is a:
+            self._pinned.move_to_end(key)
+            return t[0]
+        if t is not None:
+            self._pinned_bytes -= t[0].numel() * t[0].element_size()
+            del self._pinned[key]
+        pin = self.torch.from_numpy(a).pin_memory()
+        nb = pin.numel() * pin.element_size()
+        while self._pinned and self._pinned_bytes + nb > self.pinned_cap:
+            _, (old, _) = self._pinned.popitem(last=False)
+            self._pinned_bytes -= old.numel() * old.element_size()
+        self._pinned[key] = (pin, a)
+        self._pinned_bytes += nb
+        return pin
 
     def footprint(self, r):
         h, w = r.shape
         L = self.abf.lib()
         p = self.abf.PRECISIONS[self.precision]
-        img_b = 4 * h * w * (1 + (r.theta is not None))
+        img_b = 4 * h * w
         stack_b = int(L.abf_stack_bytes(h, w, r.N, p))
         ob = 4 if self.precision == "mixed" else 8
-        tmp_b = 4 * h * w + ob * h * w + int(L.abf_scratch_bytes(h, w, r.rho))
+        tmp_b = (4 * h * w * (1 + (r.theta is not None)) + ob * h * w +
+                 int(L.abf_scratch_bytes(h, w, r.rho)))
         return img_b, stack_b, tmp_b
 
     def launch(self, r, img_handle, stack_handle, t_admit):
@@ -339,11 +362,15 @@ class GPUExecutor:
             if img_handle is None:
                 pin = self._pin(r.f)
                 fd = pin.to(self.dev, non_blocking=True)
-                td = None
-                if r.theta is not None:
-                    td = self._pin(r.theta).to(self.dev, non_blocking=True)
-                img_handle = (fd, td, pin)
-            fd, td = img_handle[0], img_handle[1]
+                ev_img = torch.cuda.Event()
+                ev_img.record(s)
+                img_handle = (fd, ev_img)
+            else:
+                s.wait_event(img_handle[1])
+            fd = img_handle[0]
+            td = None
+            if r.theta is not None:
+                td = self._pin(r.theta).to(self.dev, non_blocking=True)
             sp = self._pin(r.sigma)
             sd = sp.to(self.dev, non_blocking=True)
             out = torch.empty((h, w), dtype=torch.float32 if p else torch.float64, device=self.dev)
@@ -352,15 +379,20 @@ class GPUExecutor:
                                     device=self.dev)
                 abf.moment_stack(fd, kernel=r.kernel, rho=r.rho, N=r.N, sigma_s=r.sigma_s,
                                  precision=self.precision, stack=stack, stream=s)
-                stack_handle = stack
-            abf.range_from_stack(stack_handle, sd, img=fd, theta=td, N=r.N, precision=self.precision,
-                                 out=out, stream=s)
+                ev_stack = torch.cuda.Event()
+                ev_stack.record(s)
+                stack_handle = (stack, ev_stack)
+            else:
+                s.wait_event(stack_handle[1])
+            abf.range_from_stack(stack_handle[0], sd, img=fd, theta=td, N=r.N,
+                                 precision=self.precision, out=out, stream=s)
             host = torch.empty((h, w), dtype=out.dtype, pin_memory=True)
             host.copy_(out, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
         # keep the transient tensors alive until the event has passed
-        return {"slot": slot, "ev": ev, "host": host, "keep": (sp, sd, out)}, img_handle, stack_handle
+        return ({"slot": slot, "ev": ev, "host": host, "keep": (sp, sd, td, out)}, img_handle,
+                stack_handle)
 
     def done(self, h):
         return h["ev"].query()

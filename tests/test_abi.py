@@ -118,3 +118,31 @@ def test_stack_single_pass_query():
     assert L.abf_stack_single_pass(16, 16, 1, -1, 6) == 0
     assert L.abf_stack_single_pass(16, 16, 1, 3, 9) == 0
     assert L.abf_stack_single_pass(16, 16, 5, 3, 6) == 0
+
+
+def test_stack_kernel_query():
+    """abf_stack_kernel names the moment kernel of a configuration: box
+    running sums, the tile kernel (LDS stride 160 or 256) or the matrix-core
+    kernel; -1 for invalid arguments."""
+    L = abf.lib()
+    BOUNDS, BOX, TILE, WIDE, MFMA = 0, 1, 2, 3, 4
+    assert L.abf_stack_kernel(4096, 4096, 0, 5, 8, 1) == BOX
+    assert L.abf_stack_kernel(4096, 4096, 0, 20, 6, 0) == BOX
+    assert L.abf_stack_kernel(4096, 4096, 0, 5, 7, 0) == TILE          # FP64 box, N >= 7
+    assert L.abf_stack_kernel(4096, 4096, 0, 40, 8, 0) == WIDE
+    assert L.abf_stack_kernel(1024, 1024, 1, 15, 6, 1) == TILE
+    assert L.abf_stack_kernel(2048, 2048, 1, 15, 6, 1) == MFMA
+    assert L.abf_stack_kernel(2048, 2048, 1, 15, 6, 0) == MFMA
+    assert L.abf_stack_kernel(2048, 2047, 1, 15, 6, 1) == TILE         # below 2^22 pixels
+    assert L.abf_stack_kernel(2048, 2048, 1, 15, 7, 1) == TILE         # N = 7 stays on the tile
+    assert L.abf_stack_kernel(2048, 2048, 1, 7, 6, 1) == TILE          # R < 8
+    assert L.abf_stack_kernel(2048, 2048, 1, 17, 6, 1) == WIDE
+    assert L.abf_stack_kernel(64, 64, 1, 16, 5, 1) == TILE
+    assert L.abf_stack_kernel(64, 64, 1, 17, 5, 1) == WIDE
+    assert L.abf_stack_kernel(64, 64, 1, 96, 8, 0) == WIDE
+    assert L.abf_stack_kernel(64, 64, 0, 3, 0, 1) == BOUNDS
+    assert L.abf_stack_kernel(0, 64, 0, 3, 5, 1) == -1
+    assert L.abf_stack_kernel(64, 64, 2, 3, 5, 1) == -1
+    assert L.abf_stack_kernel(64, 64, 0, 3, 9, 1) == -1
+    assert L.abf_stack_kernel(64, 64, 0, 97, 5, 1) == -1
+    assert L.abf_stack_kernel(64, 64, 0, 3, 5, 2) == -1

@@ -204,7 +204,7 @@ def vor4096():
 
 
 @pytest.mark.parametrize("R", [5, 20])
-@pytest.mark.parametrize("N", [5, 8])
+@pytest.mark.parametrize("N", [5, 6, 7, 8])
 def test_fast_voronoi4096_sampled(torch, abf, vor4096, R, N):
     wl = WORKLOADS[f"voronoi4096_box{R}_n{N}"]()
     assert np.array_equal(wl["f"], vor4096)
@@ -393,10 +393,12 @@ def test_fused_equals_stack_path(torch, abf, precision, kernel, R, N):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("R,N", [(12, 8), (8, 5), (16, 6)])
 def test_fast_gaussian_large_image_sampled(torch, abf, precision, R, N):
-    """Wide Gaussian windows on a 2048 x 2048 image (the size at which the
-    moment stage runs on the matrix cores), sampled pixels against the oracle,
-    edges, corners and the last partial 16-row block included."""
+    """Wide Gaussian windows on a 2048 x 2040 image, just below the size at
+    which the moment stage moves to the matrix cores: the tile kernel at a
+    large size, sampled pixels against the oracle, edges, corners and the
+    last partial tile included. (The matrix-core kernel has its own tests.)"""
     from synth import gauss_field
+    assert abf.stack_kernel(2048, 2040, "gaussian", R, N, precision) in ("tile", "tile_wide")
     f = gauss_field(77 + R, 2048, 2040)
     sg = smooth_field(np.random.default_rng(R), *f.shape, 5, 60)
     th = (f + smooth_field(np.random.default_rng(R + 1), *f.shape, -20, 20)).astype(np.float32)

@@ -110,3 +110,44 @@ def test_gpu_mix_equals_alone():
         alone = abf.fast(torch.from_numpy(q.f).cuda(), torch.from_numpy(np.ascontiguousarray(q.sigma)).cuda(),
                          kernel=q.kernel, rho=q.rho, N=q.N, sigma_s=q.sigma_s).cpu().numpy()
         assert np.array_equal(r.out, alone), q.id
+
+
+@pytest.mark.gpu
+def test_gpu_overlapping_reuse_full_size():
+    """Requests that share one image (and its moment stack) arrive together
+    and run on different slots at once: a later request must wait for the
+    upload and the stack built by an earlier one on another stream. Full
+    size (a 2048 x 2731 request of the serving workload), every request with
+    its own sigma and theta; each served result equals the same request run
+    alone, and sampled pixels of two of them match the CPU oracle."""
+    import torch
+    import oracle
+    import paper_1811_02308_amd as abf
+    from paper_1811_02308_amd.serve import GPUExecutor
+    from synth.generators import rect_scene, smooth_field
+    h, w = 2048, 2731
+    f = rect_scene(5151, h, w, side_lo=h // 16, side_hi=h // 2)
+    reqs = []
+    for i in range(8):
+        sg = smooth_field(np.random.default_rng(100 + i), h, w, 10, 30)
+        th = None if i % 2 == 0 else (f + smooth_field(np.random.default_rng(200 + i), h, w,
+                                                       -20, 20)).astype(np.float32)
+        kern, R, N = ("gaussian", 10, 6) if i < 6 else ("box", 20, 8)
+        reqs.append(Request(id=i, t_arrival=0.0, image_id="shared", f=f, sigma=sg, theta=th,
+                            kernel=kern, sigma_s=R / 3.0 if kern == "gaussian" else 0.0, rho=R, N=N))
+    srv = Server(GPUExecutor(n_slots=4), 8 << 30)
+    res = srv.run(reqs)
+    assert all(r.ok for r in res), [r.error for r in res if not r.ok]
+    assert sum(r.stack_hit for r in res) >= 4
+    fd = torch.from_numpy(f).cuda()
+    for q, r in zip(reqs, res):
+        th = None if q.theta is None else torch.from_numpy(q.theta).cuda()
+        alone = abf.fast(fd, torch.from_numpy(q.sigma).cuda(), theta=th, kernel=q.kernel, rho=q.rho,
+                         N=q.N, sigma_s=q.sigma_s).cpu().numpy()
+        assert np.array_equal(r.out, alone), q.id
+    rng = np.random.default_rng(9)
+    ys, xs = rng.integers(0, h, 200), rng.integers(0, w, 200)
+    for q, r in ((reqs[1], res[1]), (reqs[7], res[7])):
+        ref = oracle.fast_abf(f, q.theta, q.sigma, q.kernel, q.rho, q.N, sigma_s=q.sigma_s,
+                              pixels=(ys, xs))
+        assert np.max(np.abs(r.out.astype(np.float64)[ys, xs] - ref)) < 0.05
