@@ -18,9 +18,19 @@ the Gaussian tile kernel the stack is one launch that also takes the window
 bounds. The mixed-precision path is the headline value; the
 all-FP64 path, the fused variant (abf_minmax -> abf_moments_range, moments
 and range stage in one kernel, no moment planes in HBM) and the GPU brute
-force are timed beside it. The cpu_baseline leg times the CPU oracle on a
-bounded sample of the workload's pixels, and its values at those pixels
-give the parity of both GPU paths (null with --no-cpu-baseline).
+force are timed beside it. Before any step is counted, every path runs a
+fixed PREWARM_STEPS untimed steps on top of --warmup (a kernel runs slower
+in the first few hundred launches of a process).
+
+The CPU legs run before the GPU is touched (so the worker processes fork
+from a process without a HIP context): Algorithm 1 exactly as printed
+(``oracle.fast_abf_literal``) timed on a band of image rows on one host
+thread and on one band per host core at once (a pool of forked processes,
+one thread each), and the value-of-record oracle on a random sample of
+pixels, whose values give the parity of both GPU paths (all null with
+--no-cpu-baseline). A short serving stream (continuous batching of mixed
+requests, p50/p99 at three offered loads) runs after the filter timing
+(--serving-requests 0 skips it).
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -40,7 +50,9 @@ if ROOT not in sys.path:
 METRIC = "Mpix/s fast-ABF mixed vs all-FP64 on GPU at max err≤0.05/255; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
-DEFAULT_WORKLOAD = "sharpen1024_gauss15_n6"
+DEFAULT_WORKLOAD = "voronoi4096_box5_n8"
+PREWARM_STEPS = 300           # untimed steps per path before the counted warm-up
+MAX_POOL = 16                 # host processes of the all-core CPU leg (the GPU machine's CPU share)
 N_STREAMS = 2                  # images in flight in the timed steps (default of --streams)
 
 
@@ -132,28 +144,115 @@ def measured_traffic(workload: str, stage: str):
     return None
 
 
+def _literal_band(job):
+    """One row band of Algorithm 1 as printed (``oracle.fast_abf_literal``)
+    on one host thread: the band plus R rows of halo on each side (so its
+    rows equal the whole image's), returns the seconds taken."""
+    f, th, sg, kernel, R, N, ss, y0, rows = job
+    import oracle
+    H = f.shape[0]
+    lo, hi = max(0, y0 - R), min(H, y0 + rows + R)
+    with one_host_thread():
+        t0 = time.perf_counter()
+        oracle.fast_abf_literal(f[lo:hi], None if th is None else th[lo:hi], sg[lo:hi], kernel, R,
+                                N, sigma_s=ss)
+        return time.perf_counter() - t0
+
+
+def host_cores():
+    """Cores this process may run on, and the pool size the all-core leg
+    uses (at most MAX_POOL)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:                     # pragma: no cover
+        n = os.cpu_count() or 1
+    return n, max(1, min(n, MAX_POOL))
+
+
+def cpu_legs(wl, cpu_seconds: float, literal_seconds: float):
+    """The CPU oracle on the machine's host (see the module docstring). Returns
+    (cpu_baseline dict, parity pixels (ys, xs), oracle values there)."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle
+    f, th, sg = wl["f"], wl["theta"], wl["sigma"]
+    H, W = f.shape
+    R, N, kernel, ss = wl["R"], wl["N"], wl["kernel"], wl["sigma_s"]
+    visible, pool_n = host_cores()
+    # literal route, one thread: size the band to about literal_seconds
+    probe_rows = max(4, min(H, 16))
+    t_probe = _literal_band((f, th, sg, kernel, R, N, ss, H // 2, probe_rows))
+    rows = int(max(probe_rows, min(H // pool_n, literal_seconds / max(t_probe / probe_rows, 1e-9))))
+    y0 = (H - rows) // 2
+    t1 = _literal_band((f, th, sg, kernel, R, N, ss, y0, rows))
+    rate1 = rows * W / t1 / 1e6
+    # the same band size on every pool process at once (disjoint bands)
+    starts = [min(H - rows, (i * H) // pool_n) for i in range(pool_n)]
+    jobs = [(f, th, sg, kernel, R, N, ss, s, rows) for s in starts]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(pool_n) as pool:
+        pool.map(int, range(pool_n))           # processes started before the clock
+        t0 = time.perf_counter()
+        pool.map(_literal_band, jobs)
+        tall = time.perf_counter() - t0
+    rate_all = pool_n * rows * W / tall / 1e6
+    # value-of-record route on random pixels: the parity reference
+    rng = np.random.default_rng(7)
+    with one_host_thread():
+        probe = 4000
+        py = np.concatenate([[0, 0, H - 1, H - 1], rng.integers(0, H, probe)])
+        px = np.concatenate([[0, W - 1, 0, W - 1], rng.integers(0, W, probe)])
+        oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(py[:64], px[:64]))
+        t0 = time.perf_counter()
+        pref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(py, px))
+        per_px = (time.perf_counter() - t0) / len(py)
+        m = int(max(probe, min(H * W, cpu_seconds / max(per_px, 1e-9))))
+        sy, sx = rng.integers(0, H, m), rng.integers(0, W, m)
+        t0 = time.perf_counter()
+        sref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(sy, sx))
+        dt = time.perf_counter() - t0
+    cpu = {"value": round(rate_all, 4), "unit": "Mpix/s", "cores": pool_n, "kind": "oracle",
+           "sample": f"Algorithm 1 as printed (FP64 NumPy, convolutions + binomial shift + integer "
+                     f"A^-1 + erf/recursion) on {pool_n} disjoint {rows}-row bands of the same "
+                     f"{H}x{W} workload at once, one process per core, one thread each, "
+                     f"{tall:.1f} s",
+           "single_core": {"value": round(rate1, 4), "unit": "Mpix/s", "cores": 1,
+                           "sample": f"one {rows}-row band, one thread, {t1:.1f} s"},
+           "host_cores_visible": visible,
+           "value_of_record_route": {"value": round(m / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1,
+                                     "sample": f"{m} random pixels, one thread, {dt:.1f} s "
+                                               f"(also the parity reference)"}}
+    ys, xs = np.concatenate([py, sy]), np.concatenate([px, sx])
+    return cpu, (ys, xs), np.concatenate([pref, sref])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # (5000 steps of the default workload time about a quarter of a second;
-    # with 1000 the two-stream rate moved by 4-5% from run to run and read
-    # 3% low, the two streams' pipeline taking a while to settle)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=1000)
+    # (1000 steps of the default 4096 x 4096 workload take about half a
+    # second per path and stream configuration)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--streams", type=int, default=N_STREAMS,
                     help="streams the timed steps alternate between (1 for profiling: "
                          "kernels that overlap report stretched durations)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="seconds of the value-of-record oracle on sampled pixels (parity)")
+    ap.add_argument("--literal-seconds", type=float, default=6.0,
+                    help="seconds of one thread of the printed Algorithm 1 on its row band")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device-to-device copy (counter calibration for profiles)")
     ap.add_argument("--paper-maps", action="store_true",
                     help="the applications with the paper's parameter maps (sharpening, texture procedure)")
     ap.add_argument("--classical", action="store_true",
                     help="classical-filter sweep over rho and N (timing and PSNR tables) instead of the headline")
-    ap.add_argument("--serving-requests", type=int, default=0,
-                    help="also run the serving stream (p50/p99 at 3 offered loads) with this many requests")
+    ap.add_argument("--precision-table", action="store_true",
+                    help="the 4096 x 4096 Voronoi precision sweep (box rho 5 and 20, N = 5..8): "
+                         "mixed vs FP64 error per N instead of the headline")
+    ap.add_argument("--serving-requests", type=int, default=400,
+                    help="requests per offered load of the serving stream (p50/p99 at 3 loads); 0 skips it")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -162,10 +261,21 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    from synth import workload
+    wl = None
+    cpu, par_px, par_ref = None, None, None
+    if args.precision_table:
+        return precision_table(args)
+    if not (args.workload.startswith("texture") or args.classical or args.paper_maps):
+        wl = workload(args.workload)
+        if not args.no_cpu_baseline:
+            log("CPU legs (printed Algorithm 1 on row bands; value-of-record oracle on sampled pixels) ...")
+            cpu, par_px, par_ref = cpu_legs(wl, args.cpu_seconds, args.literal_seconds)
+
     import torch
 
     import paper_1811_02308_amd as abf
-    from synth import workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -182,7 +292,6 @@ def main():
         return classical_bench(args)
     if args.paper_maps:
         return paper_maps_bench(args)
-    wl = workload(args.workload)
     f, th, sg = wl["f"], wl["theta"], wl["sigma"]
     H, W = f.shape
     R, N, kernel, ss = wl["R"], wl["N"], wl["kernel"], wl["sigma_s"]
@@ -244,7 +353,7 @@ def main():
         cur = torch.cuda.current_stream()
         for st in streams:
             st.wait_stream(cur)
-        for i in range(warmup):
+        for i in range(PREWARM_STEPS + warmup):
             step(i % n_streams, streams[i % n_streams])
         torch.cuda.synchronize()
         # timed region: K steps issued back to back, alternating between the
@@ -325,36 +434,22 @@ def main():
                  "launch_ms": round(stages[dom], 5),
                  "algorithmic_bytes": model[dom]["bytes"], "algorithmic_flops": model[dom]["flops"]})
 
-    # ---------------------------------------------------------- CPU oracle baseline
-    # The cpu_baseline leg: the CPU oracle, one host thread, on a bounded
-    # random sample of this workload's pixels (plus the four corners), about
-    # --cpu-seconds of work. Its values at those pixels also give the GPU
-    # paths' parity (max |error| on [0, 255]); without the leg both are null.
-    cpu, err_m, err_d, n_par = None, None, None, 0
-    if not args.no_cpu_baseline:
-        import oracle
-        rng = np.random.default_rng(7)
-        with one_host_thread():
-            probe = 500
-            py = np.concatenate([[0, 0, H - 1, H - 1], rng.integers(0, H, probe)])
-            px = np.concatenate([[0, W - 1, 0, W - 1], rng.integers(0, W, probe)])
-            t0 = time.perf_counter()
-            pref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(py, px))
-            per_px = (time.perf_counter() - t0) / len(py)
-            m = int(max(probe, min(H * W, args.cpu_seconds / max(per_px, 1e-9))))
-            sy, sx = rng.integers(0, H, m), rng.integers(0, W, m)
-            log(f"CPU oracle on {m} sampled pixels ...")
-            t0 = time.perf_counter()
-            sref = oracle.fast_abf(f, th, sg, kernel, R, N, sigma_s=ss, pixels=(sy, sx))
-            dt = time.perf_counter() - t0
-        cpu = {"value": round(m / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-               "sample": f"{m} random pixels of the same {H}x{W} workload, value-of-record "
-                         f"oracle route, 1 thread, {dt:.1f} s"}
-        ys, xs = np.concatenate([py, sy]), np.concatenate([px, sx])
-        ref = np.concatenate([pref, sref])
-        err_m = float(np.max(np.abs(out_m.cpu().numpy().astype(np.float64)[ys, xs] - ref)))
-        err_d = float(np.max(np.abs(out_d.cpu().numpy()[ys, xs] - ref)))
+    # ---------------------------------------------------------- parity (CPU legs' oracle values)
+    err_m = err_d = None
+    n_par = 0
+    if par_ref is not None:
+        ys, xs = par_px
+        err_m = float(np.max(np.abs(out_m.cpu().numpy().astype(np.float64)[ys, xs] - par_ref)))
+        err_d = float(np.max(np.abs(out_d.cpu().numpy()[ys, xs] - par_ref)))
         n_par = int(len(ys))
+    # whole path at the roofline: the algorithmic bytes of one step (read f,
+    # theta-or-f and sigma, write the output, write and read the moment
+    # stack once) over the step's wall time
+    path_bytes = H * W * (16 + 8 * (N + 2))
+    path_gbs = path_bytes / (ms_m * 1e-3) / 1e9
+    whole = {"bound": "hbm", "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(path_gbs / HBM_PEAK_GBS, 4), "bytes_per_step": path_bytes,
+             "bytes_per_pixel": 16 + 8 * (N + 2)}
 
     lat_m = np.array(tot_m)
     res = {
@@ -390,13 +485,83 @@ def main():
                           "stage_ms_fp64": {k: round(med(v), 5) for k, v in st_sd.items()},
                           "output_equals_stack_path": fused_equal},
         "roofline": roof,
+        "whole_path_roofline": whole,
+        "prewarm_steps": PREWARM_STEPS,
         "cpu_baseline": cpu,
     }
     if args.serving_requests > 0:
         from paper_1811_02308_amd.serve import bench as serve_bench
         log("serving stream ...")
         res["serving"] = serve_bench(n=args.serving_requests, warm=max(10, args.serving_requests // 10))
+        res["serving"]["config"] = ("Poisson stream of mixed requests (sides 256-2048, 1:1 or 4:3, "
+                                    "rho 3/5/10/20, N 5/6/8, box or Gaussian), mixed precision, "
+                                    "4 slots, 16 GB budget, host copies included")
     print(json.dumps(res), flush=True)
+
+
+def precision_table(args):
+    """The precision sweep on the 4096 x 4096 Voronoi workload: box kernel,
+    rho in {5, 20}, N = 5..8, mixed and FP64 paths on one stream. Per
+    configuration: the median event-timed time of a whole fast-filter call
+    (both paths), the largest |mixed - FP64| over every pixel, and both
+    paths' largest error against the CPU oracle on sampled pixels (corners,
+    edge midpoints and random pixels)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1811_02308_amd as abf
+    from synth import workload
+
+    torch.cuda.set_device(0)
+    abf.lib()
+    rows = []
+    npx = 1500
+    for R in (5, 20):
+        for N in (5, 6, 7, 8):
+            wl = workload(f"voronoi4096_box{R}_n{N}")
+            f, sg = wl["f"], wl["sigma"]
+            H, W = f.shape
+            fd, sd = torch.from_numpy(f).cuda(), torch.from_numpy(sg).cuda()
+            outs, ms = {}, {}
+            for prec in ("mixed", "fp64"):
+                ws = torch.empty(abf.workspace_bytes(H, W, R, N, prec), dtype=torch.uint8, device="cuda")
+                out = torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64,
+                                  device="cuda")
+                call = lambda: abf.fast(fd, sd, kernel="box", rho=R, N=N, precision=prec, out=out,
+                                        workspace=ws)
+                for _ in range(PREWARM_STEPS // 3):
+                    call()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(max(5, min(args.steps, 30))):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    call()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                ms[prec] = float(np.median(ts))
+                outs[prec] = out.double().cpu().numpy()
+            rng = np.random.default_rng(11 + R + N)
+            ys = np.concatenate([[0, 0, H - 1, H - 1, H // 2, 0, H - 1, H // 2],
+                                 rng.integers(0, H, npx)])
+            xs = np.concatenate([[0, W - 1, 0, W - 1, 0, W // 2, W // 2, W - 1],
+                                 rng.integers(0, W, npx)])
+            ref = oracle.fast_abf(f, None, sg, "box", R, N, pixels=(ys, xs))
+            row = {"rho": R, "N": N,
+                   "mixed_ms": round(ms["mixed"], 4), "fp64_ms": round(ms["fp64"], 4),
+                   "mixed_mpix_s": round(H * W / 1e3 / ms["mixed"], 1),
+                   "fp64_mpix_s": round(H * W / 1e3 / ms["fp64"], 1),
+                   "max_abs_mixed_minus_fp64_all_pixels": float(np.max(np.abs(outs["mixed"] - outs["fp64"]))),
+                   "mixed_max_abs_err_vs_oracle": float(np.max(np.abs(outs["mixed"][ys, xs] - ref))),
+                   "fp64_max_abs_err_vs_oracle": float(np.max(np.abs(outs["fp64"][ys, xs] - ref))),
+                   "oracle_pixels": int(len(ys))}
+            log(row)
+            rows.append(row)
+    print(json.dumps({"metric": "precision sweep, mixed vs FP64 error per N",
+                      "config": {"workload": "voronoi4096 box rho 5/20, N 5..8 (one fast-filter call, one stream)"},
+                      "rows": rows}), flush=True)
 
 
 def classical_bench(args):

@@ -86,6 +86,14 @@ struct Batch {
   long long out = 0;
 };
 
+// p[i] for a wave-uniform base p and a per-lane 32-bit byte offset (the
+// load then takes the base from scalar registers and the offset from one
+// vector register, with no 64-bit address arithmetic per lane).
+template <typename T>
+__device__ __forceinline__ T at_byte(const T* p, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ T* byte_offset(T* p, long long bytes) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<void*>(static_cast<const void*>(p))) + bytes);

@@ -281,57 +281,18 @@ __device__ __forceinline__ void recompute_flagged(unsigned long long mask, bool 
 // columns j0 + lane for the kChunks chunks j0 = 0, 64, ...: issued early so
 // the loads overlap the row's other work.
 constexpr int kChunks = kStrip / kWave;
-static_assert(kChunks == 4, "epilogue_row selects among four bound registers");
+static_assert(kChunks == 4, "the box epilogue selects among four bound registers");
 __device__ __forceinline__ void load_bounds_row(const float* __restrict__ alpha,
                                                 const float* __restrict__ beta, long long sp,
                                                 int y, int xo, int O, int W, int lane,
                                                 float (&pa)[kChunks], float (&pb)[kChunks]) {
+  const float* ar = alpha + (long long)y * sp;
+  const float* br = beta + (long long)y * sp;
 #pragma unroll
   for (int q = 0; q < kChunks; ++q) {
-    const int j = q * kWave + lane;
-    const int x = min(xo + min(j, O - 1), W - 1);
-    pa[q] = alpha[(long long)y * sp + x];
-    pb[q] = beta[(long long)y * sp + x];
-  }
-}
-
-// Epilogue for one output row of a wave: lanes take consecutive output
-// columns j0 + lane; `sum_k(j, k)` returns the normalised window moment of
-// u^(k+1) for strip column j; pa/pb hold the row's bounds
-// (load_bounds_row). Ill-conditioned pixels are recomputed by the whole
-// wave with direct_legendre.
-template <int N, typename TS, bool FUSED, typename SumFn>
-__device__ __forceinline__ void epilogue_row(SumFn sum_k, int y, int xo, int O, int W, int H,
-                                             int R, const float* __restrict__ img, long long pitch,
-                                             const float (&pa)[kChunks],
-                                             const float (&pb)[kChunks], long long sp,
-                                             double c, double cond_max,
-                                             const double* __restrict__ wts, double norm,
-                                             TS* __restrict__ mom, long long plane, int lane,
-                                             const FuseArgs& fz) {
-  for (int q = 0; q < kChunks; ++q) {
-    const int j0 = q * kWave;
-    if (j0 >= O) break;
-    const int j = j0 + lane;
-    const bool valid = j < O && xo + j < W;
-    const int x = valid ? xo + j : xo;
-    const long long idx = (long long)y * sp + x;
-    float a = 0.f, b = 0.f;
-    bool bad = false;
-    double m[N + 1];
-    if (valid) {
-      m[0] = 1.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) m[k + 1] = sum_k(j, k);
-      a = q == 0 ? pa[0] : q == 1 ? pa[1] : q == 2 ? pa[2] : pa[3];
-      b = q == 0 ? pb[0] : q == 1 ? pb[1] : q == 2 ? pb[2] : pb[3];
-      bad = legendre_from_moments<N>(m, a, b, c, cond_max);
-      if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
-    }
-    const unsigned long long mask = __ballot(valid && bad);
-    if (mask)
-      recompute_flagged<N, TS, FUSED>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R, wts, norm,
-                                      mom, plane, sp, lane, fz);
+    const unsigned x = (unsigned)min(xo + min(q * kWave + lane, O - 1), W - 1);
+    pa[q] = ar[x];
+    pb[q] = br[x];
   }
 }
 
@@ -353,6 +314,71 @@ __device__ __forceinline__ double wave_origin(const float* __restrict__ alpha,
   return 0.5 * ((double)lo + (double)hi);
 }
 
+// Origin of the box kernel's power sums: the mid-range of the input values
+// sampled on an 8 x 8 grid over the wave's output tile. It depends on the
+// input only, so the stack is the same whether the kernel takes the window
+// bounds itself or reads them.
+__device__ __forceinline__ double input_origin(const float* __restrict__ img, long long pitch,
+                                               int y0, int y1, int xo, int O, int W, int lane,
+                                               const FinMinMax& fm) {
+  const int gy = lane >> 3, gx = lane & 7;
+  const int yy = min(y0 + (gy * (y1 - 1 - y0)) / 7, y1 - 1);
+  const int xx = min(xo + (gx * (O - 1)) / 7, W - 1);
+  float lo = img[(long long)yy * pitch + xx] + 0.0f;
+  float hi = lo;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    lo = fm.min(lo, __shfl_xor(lo, off, kWave));
+    hi = fm.max(hi, __shfl_xor(hi, off, kWave));
+  }
+  return 0.5 * ((double)lo + (double)hi);
+}
+
+// Shift and Legendre change from raw window sums: m[1..N] are the sums of
+// u^k over the window, u = f - c, and area the number of taps (box weights
+// 1/area). Same steps as legendre_from_moments, with the normalisation
+// folded into the final scaling (the shift is homogeneous in the sums, so
+// it runs on the raw sums with m_0 = area).
+template <int N>
+__device__ __forceinline__ bool legendre_from_sums(double (&m)[N + 1], float a, float b,
+                                                   double c, double cond_max, double area,
+                                                   double inv_area) {
+  constexpr LegTable LT{};
+  const double mid = 0.5 * ((double)a + (double)b) - c;
+  const double half = 0.5 * ((double)b - (double)a);
+  const double ih = rcp(half);
+  const double rho = fma(fabs(mid), ih, 1.0);
+  double rn = rho;
+#pragma unroll
+  for (int k = 1; k < N; ++k) rn *= rho;
+  if (!(rn <= cond_max)) return true;
+  const double s = -mid;
+  m[0] = area;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int k = N; k > j; --k) m[k] = fma(s, m[k - 1], m[k]);
+  double sc = ih * inv_area;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    m[k] *= sc;
+    sc *= ih;
+  }
+  double out[N + 1];
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = k; r >= 1; r -= 2) acc = fma(LT.L[k][r], m[r], acc);
+    // (r = 0 contributes L[k][0] nu_0 = L[k][0] for even k)
+    if ((k & 1) == 0) acc += LT.L[k][0];
+    out[k] = acc;
+  }
+#pragma unroll
+  for (int k = 1; k <= N; ++k) m[k] = out[k];
+  return false;
+}
+
 struct StripGeom {
   int O;       // output columns per strip
   int Rpad;    // R rounded up to a multiple of kV
@@ -361,13 +387,22 @@ struct StripGeom {
   int n_segs;
 };
 
+// Slot of the exclusive prefix P(-1) = 0 in each power's LDS row (pidx(-1):
+// a padding slot of the third column row, never written by the scan).
+constexpr int kZeroSlot = 2 * kSlotStride + kSlotStride - 1;
+static_assert(kZeroSlot == ((-1) & (kV - 1)) * kSlotStride + ((-1) >> 2), "pidx(-1)");
+
+// One wave per workgroup: the LDS of a wave (its N prefix rows) then
+// limits occupancy with no rounding to four-wave groups.
+constexpr int kBoxWaves = 1;
+
 template <int N, typename TS, bool FUSED>
-__global__ __launch_bounds__(kWaves * kWave) void moments_box(
+__global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
     TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4, Batch bt,
     FuseArgs fz) {
-  __shared__ double sh[kWaves][N][kStripSlots];
+  __shared__ double sh[kBoxWaves][N][kStripSlots];
   img += blockIdx.y * bt.img;
   if (FUSED) {
     fz.theta += blockIdx.y * bt.img;
@@ -379,15 +414,18 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
   mom = byte_offset(mom, blockIdx.y * bt.stack);
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
-  const int gw = blockIdx.x * kWaves + wv;
+  const int gw = blockIdx.x * kBoxWaves + wv;
   if (gw >= g.n_strips * g.n_segs) return;
+  const FinMinMax fm;
   const int strip = gw % g.n_strips;
   const int seg = gw / g.n_strips;
   const int y0 = seg * g.TH;
   const int y1 = min(H, y0 + g.TH);
   const int xo = strip * g.O;            // first output column of the strip
   const int xs = xo - g.Rpad;            // padded column 0
-  const double c = wave_origin(alpha, beta, sp, y0, y1, xo, g.O, W, lane);
+  const double c = input_origin(img, pitch, y0, y1, xo, g.O, W, lane, fm);
+  double (*const shw)[kStripSlots] = sh[wv];
+  if (lane < N) shw[lane][kZeroSlot] = 0.0;
 
   int cx[kV];
 #pragma unroll
@@ -427,7 +465,8 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
     }
   }
 
-  const double inv_area = 1.0 / ((double)(2 * R + 1) * (double)(2 * R + 1));
+  const double area = (double)(2 * R + 1) * (double)(2 * R + 1);
+  const double inv_area = 1.0 / area;
   // the rows entering and leaving the window at y + 1, loaded one row ahead
   float qi[kV], qo[kV];
   auto load_step = [&](int yn) {
@@ -459,7 +498,7 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
         }
       }
     }
-    // horizontal: inclusive prefix of the vertical sums along the strip
+    // horizontal sums: inclusive prefix of the vertical sums along the strip
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       double p0 = S[k][0];
@@ -468,21 +507,43 @@ __global__ __launch_bounds__(kWaves * kWave) void moments_box(
       double p3 = p2 + S[k][3];
       const double incl = wave_inclusive_scan(p3, lane);
       const double ex = incl - p3;
-      double* d = sh[wv][k];
+      double* d = shw[k];
       d[pidx(kV * lane + 0)] = ex + p0;
       d[pidx(kV * lane + 1)] = ex + p1;
       d[pidx(kV * lane + 2)] = ex + p2;
       d[pidx(kV * lane + 3)] = incl;
     }
     wave_sync();
-    auto sum_k = [&](int j, int k) -> double {
-      const int e = g.Rpad + j;
-      const double hi = sh[wv][k][pidx(e + R)];
-      const double lo = (e - R - 1 >= 0) ? sh[wv][k][pidx(e - R - 1)] : 0.0;
-      return (hi - lo) * inv_area;
-    };
-    epilogue_row<N, TS, FUSED>(sum_k, y, xo, g.O, W, H, R, img, pitch, pa, pb, sp, c,
-                               cond_max, nullptr, inv_area, mom, plane, lane, fz);
+    // epilogue: lanes take consecutive output columns
+    for (int q = 0; q < kChunks; ++q) {
+      const int j0 = q * kWave;
+      if (j0 >= g.O) break;
+      const int j = j0 + lane;
+      const bool valid = j < g.O && xo + j < W;
+      const int x = valid ? xo + j : xo;
+      const int e = g.Rpad + (valid ? j : 0);
+      const float a = q == 0 ? pa[0] : q == 1 ? pa[1] : q == 2 ? pa[2] : pa[3];
+      const float b = q == 0 ? pb[0] : q == 1 ? pb[1] : q == 2 ? pb[2] : pb[3];
+      const long long idx = (long long)y * sp + x;
+      bool bad = false;
+      if (valid) {
+        double m[N + 1];
+        const int eh = e + R, el = e - R - 1;
+#pragma unroll
+        for (int k = 0; k < N; ++k) m[k + 1] = shw[k][pidx(eh)] - shw[k][pidx(el)];
+        if (a == b) {
+#pragma unroll
+          for (int k = 1; k <= N; ++k) m[k] = 0.0;
+        } else {
+          bad = legendre_from_sums<N>(m, a, b, c, cond_max, area, inv_area);
+        }
+        if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
+      }
+      const unsigned long long mask = __ballot(valid && bad);
+      if (mask)
+        recompute_flagged<N, TS, FUSED>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R,
+                                        nullptr, inv_area, mom, plane, sp, lane, fz);
+    }
     wave_sync();
   }
 }
@@ -1208,10 +1269,10 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   static const long long capacity = [] {
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, moments_box<N, TS, false>,
-                                                     kWaves * kWave, 0) !=
+                                                     kBoxWaves * kWave, 0) !=
             hipSuccess || blocks < 1)
-      blocks = 2;
-    return (long long)blocks * kWaves * device_cus();
+      blocks = 8;
+    return (long long)blocks * kBoxWaves * device_cus();
   }();
   const StripGeom g = make_geom(h, w, R, capacity);
   // largest tolerated shift amplification rho^N before a pixel is taken
@@ -1240,15 +1301,15 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     fz.gl = make_gl_args(sizeof(TS) == 4);
   }
   if (kind == 0 && !box_tile) {
-    dim3 grid((waves + kWaves - 1) / kWaves, b.n);
+    dim3 grid((waves + kBoxWaves - 1) / kBoxWaves, b.n);
     const int vec4 = (pitch % 4 == 0) && (b.img % 4 == 0) &&
                      (reinterpret_cast<uintptr_t>(img) % 16 == 0);
     if (fs)
-      hipLaunchKernelGGL((moments_box<N, TS, true>), grid, dim3(kWaves * kWave), 0, stream, img,
-                         pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b, fz);
+      hipLaunchKernelGGL((moments_box<N, TS, true>), grid, dim3(kBoxWaves * kWave), 0, stream,
+                         img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b, fz);
     else
-      hipLaunchKernelGGL((moments_box<N, TS, false>), grid, dim3(kWaves * kWave), 0, stream, img,
-                         pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b, fz);
+      hipLaunchKernelGGL((moments_box<N, TS, false>), grid, dim3(kBoxWaves * kWave), 0, stream,
+                         img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b, fz);
     return hipGetLastError();
   }
   const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);

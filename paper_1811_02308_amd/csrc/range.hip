@@ -49,7 +49,9 @@ __global__ __launch_bounds__(256) void range_kernel(
   // output's own resolution of the 0.05 tolerance); FP64 path: 16 nodes.
   constexpr bool kMixed = sizeof(TO) == 4;
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  // a wave is one row segment: its row and every row pointer below are
+  // wave-uniform (scalar registers), and each lane adds its byte offset
+  const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (x >= W || y >= H) return;
   {
     const long long z = blockIdx.z;
@@ -60,8 +62,9 @@ __global__ __launch_bounds__(256) void range_kernel(
     sigma += z * bt.img;
     out += z * bt.out;
   }
-  const long long idx = (long long)y * sp + x;
-  const float a = alpha[idx], b = beta[idx];
+  const long long row = (long long)y * sp;
+  const unsigned bx4 = (unsigned)x * 4u;
+  const float a = at_byte(alpha + row, bx4), b = at_byte(beta + row, bx4);
   TO* o = out + (long long)y * opitch + x;
   if (a == b) {
     *o = TO(a);
@@ -69,10 +72,12 @@ __global__ __launch_bounds__(256) void range_kernel(
   }
   double ak[N + 1];                      // (2k+1) a~_k
   ak[0] = 1.0;
+  const unsigned bxs = (unsigned)x * (unsigned)sizeof(TS);
 #pragma unroll
-  for (int k = 1; k <= N; ++k) ak[k] = (2.0 * k + 1.0) * (double)mom[(k - 1) * plane + idx];
-  *o = TO(range_eval<N, kMixed>(a, b, ak, (double)theta[(long long)y * tpitch + x],
-                                (double)sigma[(long long)y * spitch + x], flags, gl));
+  for (int k = 1; k <= N; ++k)
+    ak[k] = (2.0 * k + 1.0) * (double)at_byte(mom + (k - 1) * plane + row, bxs);
+  *o = TO(range_eval<N, kMixed>(a, b, ak, (double)at_byte(theta + (long long)y * tpitch, bx4),
+                                (double)at_byte(sigma + (long long)y * spitch, bx4), flags, gl));
 }
 
 

@@ -105,13 +105,30 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
   constexpr LegTable LT{};
   constexpr int Q = kMixed ? kGLNodesMixed : kGLNodes;
   const double da = a, delta = b - da;
-  const double t0 = (th - da) * rcp(delta);
-  const double lam = isinf(sg) ? 0.0 : delta * delta * rcp(2.0 * sg * sg);
+  double t0, lam, sl;
+  if (kMixed) {
+    // Mixed path: t0 and sqrt(lambda) = (beta - alpha) / (sigma sqrt 2) in
+    // FP32 (relative errors of a few 1e-8 move g^ by far less than the
+    // mixed tolerance), and lambda taken as the exact FP64 square of that
+    // FP32 root, so that every later step works on one consistent
+    // (t0, lambda) pair. sigma = +inf gives sqrt(lambda) = 0; the root is
+    // capped at 1e15 (sigma -> 0).
+    const float d32 = (float)b - (float)a;
+    const float t32 = ((float)th - (float)a) * __builtin_amdgcn_rcpf(d32);
+    const float s32 = fminf(d32 * __builtin_amdgcn_rcpf((float)sg) * 0.70710678118654752f, 1e15f);
+    t0 = t32;
+    sl = s32;
+    lam = sl * sl;
+  } else {
+    t0 = (th - da) * rcp(delta);
+    lam = isinf(sg) ? 0.0 : delta * delta * rcp(2.0 * sg * sg);
+    sl = sqrt(lam);
+  }
 
   const double ts = fmin(fmax(t0, 0.0), 1.0);
   const double dist = fabs(t0 - ts);
   double T1, T2, F0;
-  if (lam >= lam_split(N, kMixed) && dist * sqrt(lam) < outside_limit(kMixed)) {
+  if (lam >= lam_split(N, kMixed) && dist * sl < outside_limit(kMixed)) {
     double c[N + 1];
 #pragma unroll
     for (int r = 0; r <= N; ++r) {
@@ -120,7 +137,6 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
       for (int k = r; k <= N; ++k) acc = fma(ak[k], SL.ell[k][r], acc);
       c[r] = acc;
     }
-    const double sl = sqrt(lam);
     const double A = -sl * t0, B = sl * (1.0 - t0);
     const double dd = t0 - ts;
     const double s = lam * dd * dd;
@@ -157,7 +173,9 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
     }
   } else {
     // support of the scaled Gaussian exp(-lam ((t-t0)^2 - dist^2)) above e^-kSupport
-    const double L = lam > 0.0 ? sqrt(dist * dist + kSupport / lam) - dist : 2.0;
+    const double L = lam > 0.0 ? (kMixed ? (double)sqrtf((float)(dist * dist + kSupport / lam))
+                                         : sqrt(dist * dist + kSupport / lam)) - dist
+                               : 2.0;
     const double lo = fmax(0.0, ts - L), hi = fmin(1.0, ts + L);
     const double span = hi - lo;
     // p in powers of x = 2t - 1: bx[r] = sum_k ak[k] L[k][r] (coefficients of

@@ -409,6 +409,12 @@ class GPUExecutor:
 
 
 # ---------------------------------------------------------------------- benchmark
+# Scenes and sigma maps of the request pool, keyed by (h, w, index): their
+# seeds depend only on the key, so every stream draws from the same pool.
+_SCENES: dict = {}
+_SIGMAS: dict = {}
+
+
 def make_requests(seed: int, n: int, rate: float, pool: int = 12, scale: float = 1.0):
     """Poisson arrivals of filter requests (sizes, rho, N, kernel as in the
     serving workload), drawing images from a pool of ``pool`` seeded scenes
@@ -416,8 +422,8 @@ def make_requests(seed: int, n: int, rate: float, pool: int = 12, scale: float =
     import numpy as np
     from synth.generators import rect_scene, smooth_field
     rng = np.random.Generator(np.random.PCG64(seed))
-    scenes = {}
-    sigmas = {}
+    scenes = _SCENES
+    sigmas = _SIGMAS
     t = 0.0
     out = []
     for i in range(n):
@@ -444,6 +450,55 @@ def make_requests(seed: int, n: int, rate: float, pool: int = 12, scale: float =
     return out
 
 
+def breakdown(reqs, precision="mixed"):
+    """Where the saturation rate goes: the same requests' filter calls alone
+    (inputs resident, one stream, back to back), their host-device copies
+    alone (image and sigma up, result down, pinned host memory), and the
+    serving loop alone (a CPU executor that finishes every request at once)."""
+    import torch
+    import paper_1811_02308_amd as abf
+    dev = torch.device("cuda")
+    uniq = {}
+    for r in reqs:
+        uniq.setdefault(id(r.f), r.f)
+        uniq.setdefault(id(r.sigma), r.sigma)
+    resident = {k: torch.from_numpy(a).to(dev) for k, a in uniq.items()}
+    pinned = {k: torch.from_numpy(a).pin_memory() for k, a in uniq.items()}
+    px = sum(r.pixels for r in reqs)
+    outs = {}
+    for r in reqs:
+        outs.setdefault(r.shape, torch.empty(r.shape, dtype=torch.float32 if precision == "mixed"
+                                             else torch.float64, device=dev))
+
+    def compute():
+        for r in reqs:
+            abf.fast(resident[id(r.f)], resident[id(r.sigma)], kernel=r.kernel, rho=r.rho, N=r.N,
+                     sigma_s=r.sigma_s, precision=precision, out=outs[r.shape])
+
+    def copies():
+        for r in reqs:
+            resident[id(r.f)].copy_(pinned[id(r.f)], non_blocking=True)
+            resident[id(r.sigma)].copy_(pinned[id(r.sigma)], non_blocking=True)
+            host = torch.empty(r.shape, dtype=outs[r.shape].dtype, pin_memory=True)
+            host.copy_(outs[r.shape], non_blocking=True)
+
+    res = {}
+    for name, fn in (("compute_only", compute), ("copies_only", copies)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        res[name + "_mpix_per_s"] = px / (time.perf_counter() - t0) / 1e6
+    loop_reqs = [dataclasses.replace(r, t_arrival=0.0) for r in reqs]
+    ex = FakeExecutor(n_slots=4, us_per_px=0.0)
+    t0 = time.perf_counter()
+    Server(ex, 1 << 62, poll_s=0.0).run(loop_reqs, realtime=False)
+    res["loop_only_req_per_s"] = len(reqs) / (time.perf_counter() - t0)
+    res["requests"] = len(reqs)
+    return res
+
+
 def bench(loads=(0.3, 0.6, 0.9), n=300, warm=30, slots=4, budget_gb=16.0, seed=1004,
           precision="mixed", scale=1.0):
     """Measure closed-loop saturation throughput, then run Poisson streams at
@@ -459,7 +514,7 @@ def bench(loads=(0.3, 0.6, 0.9), n=300, warm=30, slots=4, budget_gb=16.0, seed=1
     sat = summarize(res, wall)
     sat_px_s = sat["mpix_per_s"] * 1e6
     mean_px = float(np.mean([r.pixels for r in sat_reqs]))
-    report = {"saturation": sat, "loads": {}}
+    report = {"saturation": sat, "loads": {}, "breakdown": breakdown(sat_reqs, precision)}
     for L in loads:
         rate = L * sat_px_s / mean_px
         reqs = make_requests(seed + int(1000 * L), n + warm, rate, scale=scale)

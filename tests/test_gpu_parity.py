@@ -300,8 +300,8 @@ SINGLE_PASS = [((256, 300), 15, 6), ((37, 300), 5, 8), ((300, 37), 20, 5), ((1, 
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("shape,R,N", SINGLE_PASS)
-def test_single_pass_stack_equals_two_pass(torch, abf, precision, shape, R, N):
+@pytest.mark.parametrize("kernel,shape,R,N", [("gaussian",) + c for c in SINGLE_PASS])
+def test_single_pass_stack_equals_two_pass(torch, abf, precision, kernel, shape, R, N):
     """Where the Gaussian tile kernel takes the window bounds itself
     (abf_stack_single_pass), abf_moment_stack equals abf_minmax followed by
     abf_stack_moments bit for bit, and its bounds are the exact window
@@ -312,12 +312,12 @@ def test_single_pass_stack_equals_two_pass(torch, abf, precision, shape, R, N):
     f[h // 3: h // 3 + 20, w // 4: w // 4 + 40] = np.float32(250.0)
     f[h // 3: h // 3 + 20, w // 4: w // 4 + 40] += (np.arange(min(40, w - w // 4), dtype=np.float32) % 3) * np.float32(0.25)
     f[::7, ::5] = np.float32(-0.0)
-    assert abf.stack_single_pass(h, w, "gaussian", R, N)
+    assert abf.stack_single_pass(h, w, kernel, R, N)
     img = dev(torch, f)
-    one = abf.moment_stack(img, kernel="gaussian", rho=R, N=N, precision=precision)
+    one = abf.moment_stack(img, kernel=kernel, rho=R, N=N, precision=precision)
     two = torch.zeros_like(one)
     abf.minmax_into_stack(img, two, R, N, precision=precision)
-    abf.stack_moments(img, two, kernel="gaussian", rho=R, N=N, precision=precision)
+    abf.stack_moments(img, two, kernel=kernel, rho=R, N=N, precision=precision)
     torch.cuda.synchronize()
     p1 = abf.stack_planes(one, h, w, N, precision)
     p2 = abf.stack_planes(two, h, w, N, precision)
