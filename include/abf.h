@@ -214,6 +214,28 @@ abf_status abf_fast(const float* img, const float* theta, const float* sigma,
                     void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * abf_fast_noalloc -- abf_fast for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Its workspace is a fixed array of
+ * ABF_NOALLOC_BYTES bytes (64 MiB) that the library holds on every GPU it
+ * runs on until the process ends; the call itself allocates nothing. A
+ * request whose abf_workspace_bytes(h, w, rho, N, precision) exceeds
+ * ABF_NOALLOC_BYTES returns ABF_E_WORKSPACE before any device work (about
+ * 16 + 4N bytes per pixel mixed, 16 + 8N FP64: 1024 x 1024 fits at every N
+ * mixed and up to N = 6 in FP64). Calls on one GPU share that GPU's array:
+ * calls that overlap on one GPU, on any streams, race, so the caller
+ * serialises them.
+ * Other arguments, checks and results are those of abf_fast (the same
+ * kernels: the output is bit-identical).
+ */
+enum { ABF_NOALLOC_BYTES = 64 << 20 };
+abf_status abf_fast_noalloc(const float* img, const float* theta, const float* sigma,
+                            int h, int w, long long pitch, int kernel_kind,
+                            double sigma_s, int rho, int N, int precision,
+                            unsigned flags, void* out, long long out_pitch,
+                            void* stream);
+
+/*
  * abf_uniform_prior -- the uniform-prior comparison variant of Sec. III-B
  * (classical filtering, Fig. 3 and the discussion beside Table 1): the
  * N = 0 estimator of Algorithm 1 with the constant fitted on

@@ -75,6 +75,7 @@ def lib():
         "abf_minmax": ([vp, i, i, ll, i, vp, vp, ll, vp, sz, vp], i),
         "abf_moment_stack": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp, sz, vp], i),
         "abf_stack_single_pass": ([i, i, i, i, i], i),
+        "abf_fast_noalloc": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, ll, vp], i),
         "abf_stack_kernel": ([i, i, i, i, i, i], i),
         "abf_stack_moments": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp], i),
         "abf_range": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
