@@ -15,9 +15,11 @@ filter parameters) arrive over time. One host thread runs the loop:
   * completed events free the slot and the request's transient memory; the
     result and its latency (completion - arrival) are recorded.
 
-Images and moment stacks are kept resident in HBM in LRU caches whose bytes
-count against the same budget (the stack depends only on the image, kernel,
-rho and N, so a request that changes only theta or sigma reuses it).
+Images, sigma maps that carry an identity (``sigma_id``) and moment stacks
+are kept resident in HBM in LRU caches whose bytes count against the same
+budget (the stack depends only on the image, kernel, rho and N, so a request
+that changes only theta or sigma reuses it; a request whose image and sigma
+map are resident moves only its result over PCIe).
 
 The device work goes through an *executor*. ``GPUExecutor`` drives the HIP
 library; ``FakeExecutor`` (tests) runs on the CPU with modelled durations, so
@@ -45,6 +47,7 @@ class Request:
     sigma: Any                           # host float32 (h, w)
     theta: Any = None
     kernel: str = "box"
+    sigma_id: Any = None                 # identity of the sigma map (cache key); None: upload
     sigma_s: float = 0.0
     rho: int = 3
     N: int = 5
@@ -119,17 +122,18 @@ class Server:
         self.budget = int(mem_budget)
         self.poll_s = poll_s
         self.images = LRUBytes()
+        self.maps = LRUBytes()
         self.stacks = LRUBytes()
         self.transient = 0
         self.max_in_use = 0
 
     # ------------------------------------------------------------------ memory
     def in_use(self) -> int:
-        return self.transient + self.images.bytes + self.stacks.bytes
+        return self.transient + self.images.bytes + self.maps.bytes + self.stacks.bytes
 
     def _make_room(self, need: int) -> bool:
         while self.in_use() + need > self.budget:
-            if not (self.stacks.evict_one() or self.images.evict_one()):
+            if not (self.stacks.evict_one() or self.maps.evict_one() or self.images.evict_one()):
                 return False
         return True
 
@@ -170,7 +174,8 @@ class Server:
                     self.ex.release(h)
                     self.transient -= nbytes
                     self.images.unhold(keys[0])
-                    self.stacks.unhold(keys[1])
+                    self.maps.unhold(keys[1])
+                    self.stacks.unhold(keys[2])
                 else:
                     still.append((r, h, t_adm, nbytes, hit, keys))
             inflight = still
@@ -178,28 +183,35 @@ class Server:
             while queue and len(inflight) < self.ex.n_slots:
                 r = queue[0]
                 skey = (r.image_id, r.kernel, r.rho, r.N, r.sigma_s)
+                mkey = r.sigma_id
                 have_img = self.images.get(r.image_id) is not None
+                have_map = mkey is not None and self.maps.get(mkey) is not None
                 have_stack = self.stacks.get(skey) is not None
-                img_b, stack_b, tmp_b = self.ex.footprint(r)
-                need = tmp_b + (0 if have_img else img_b) + (0 if have_stack else stack_b)
-                if tmp_b + img_b + stack_b > self.budget:
+                img_b, map_b, stack_b, tmp_b = self.ex.footprint(r)
+                need = (tmp_b + (0 if have_img else img_b) + (0 if have_map else map_b) +
+                        (0 if have_stack else stack_b))
+                if tmp_b + img_b + map_b + stack_b > self.budget:
                     queue.popleft()
                     results[r.id] = Result(r.id, r.t_arrival, now, now, False,
                                            error="request larger than the memory budget")
                     continue
                 # hold what this request reuses so that making room cannot evict it
                 self.images.hold(r.image_id)
+                self.maps.hold(mkey)
                 self.stacks.hold(skey)
                 if not self._make_room(need):
                     self.images.unhold(r.image_id)
+                    self.maps.unhold(mkey)
                     self.stacks.unhold(skey)
                     break
                 t_adm = now_fn()
                 try:
-                    h, img_handle, stack_handle = self.ex.launch(
-                        r, self.images.get(r.image_id), self.stacks.get(skey), t_adm)
+                    h, img_handle, map_handle, stack_handle = self.ex.launch(
+                        r, self.images.get(r.image_id),
+                        None if mkey is None else self.maps.get(mkey), self.stacks.get(skey), t_adm)
                 except Exception as e:
                     self.images.unhold(r.image_id)
+                    self.maps.unhold(mkey)
                     self.stacks.unhold(skey)
                     queue.popleft()
                     results[r.id] = Result(r.id, r.t_arrival, t_adm, t_adm, False, error=repr(e))
@@ -208,12 +220,15 @@ class Server:
                 if not have_img:
                     self.images.put(r.image_id, img_handle, img_b)
                     self.images.hold(r.image_id)
+                if mkey is not None and not have_map:
+                    self.maps.put(mkey, map_handle, map_b)
+                    self.maps.hold(mkey)
                 if not have_stack:
                     self.stacks.put(skey, stack_handle, stack_b)
                     self.stacks.hold(skey)
                 self.transient += tmp_b
                 self.max_in_use = max(self.max_in_use, self.in_use())
-                inflight.append((r, h, t_adm, tmp_b, have_stack, (r.image_id, skey)))
+                inflight.append((r, h, t_adm, tmp_b, have_stack, (r.image_id, mkey, skey)))
             if realtime:
                 if self.poll_s > 0:
                     time.sleep(self.poll_s)
@@ -259,15 +274,19 @@ class FakeExecutor:
         self.fail_at_result = set(fail_at_result)
         self.compute = compute
         self.launched = []
+        self.map_uploads = 0
         self.now = 0.0
         self._busy_until = [0.0] * n_slots
         self._slot_of = {}
 
     def footprint(self, r):
+        """(image, sigma map when cached, stack, transient) bytes."""
         px = r.pixels
-        return 4 * px, 4 * px * (r.N + 2), 8 * px + 4 * px * (r.theta is not None)
+        cached = r.sigma_id is not None
+        return (4 * px, 4 * px * cached, 4 * px * (r.N + 2),
+                4 * px + 4 * px * (not cached) + 4 * px * (r.theta is not None))
 
-    def launch(self, r, img_handle, stack_handle, t_admit):
+    def launch(self, r, img_handle, map_handle, stack_handle, t_admit):
         if r.id in self.fail_ids:
             raise RuntimeError(f"injected failure for request {r.id}")
         free = [s for s in range(self.n_slots) if self._busy_until[s] <= t_admit]
@@ -276,7 +295,10 @@ class FakeExecutor:
         dur = r.pixels * self.us_per_px * 1e-6 * (0.3 if stack_handle is not None else 1.0)
         self._busy_until[slot] = start + dur
         self.launched.append(r.id)
-        return {"r": r, "end": start + dur}, ("img", r.image_id), ("stack", r.image_id)
+        if r.sigma_id is not None and map_handle is None:
+            self.map_uploads += 1
+        return ({"r": r, "end": start + dur}, ("img", r.image_id),
+                None if r.sigma_id is None else ("map", r.sigma_id), ("stack", r.image_id))
 
     def finish_time(self, h):
         return h["end"]
@@ -346,13 +368,15 @@ class GPUExecutor:
         L = self.abf.lib()
         p = self.abf.PRECISIONS[self.precision]
         img_b = 4 * h * w
+        cached = r.sigma_id is not None
+        map_b = 4 * h * w * cached
         stack_b = int(L.abf_stack_bytes(h, w, r.N, p))
         ob = 4 if self.precision == "mixed" else 8
-        tmp_b = (4 * h * w * (1 + (r.theta is not None)) + ob * h * w +
+        tmp_b = (4 * h * w * ((not cached) + (r.theta is not None)) + ob * h * w +
                  int(L.abf_scratch_bytes(h, w, r.rho)))
-        return img_b, stack_b, tmp_b
+        return img_b, map_b, stack_b, tmp_b
 
-    def launch(self, r, img_handle, stack_handle, t_admit):
+    def launch(self, r, img_handle, map_handle, stack_handle, t_admit):
         torch, abf = self.torch, self.abf
         slot = self.free_slots.pop(0)
         s = self.streams[slot]
@@ -371,8 +395,17 @@ class GPUExecutor:
             td = None
             if r.theta is not None:
                 td = self._pin(r.theta).to(self.dev, non_blocking=True)
-            sp = self._pin(r.sigma)
-            sd = sp.to(self.dev, non_blocking=True)
+            sp = None
+            if map_handle is not None:
+                s.wait_event(map_handle[1])
+                sd = map_handle[0]
+            else:
+                sp = self._pin(r.sigma)
+                sd = sp.to(self.dev, non_blocking=True)
+                if r.sigma_id is not None:
+                    ev_map = torch.cuda.Event()
+                    ev_map.record(s)
+                    map_handle = (sd, ev_map)
             out = torch.empty((h, w), dtype=torch.float32 if p else torch.float64, device=self.dev)
             if stack_handle is None:
                 stack = torch.empty(int(abf.lib().abf_stack_bytes(h, w, r.N, p)), dtype=torch.uint8,
@@ -392,7 +425,7 @@ class GPUExecutor:
             ev.record(s)
         # keep the transient tensors alive until the event has passed
         return ({"slot": slot, "ev": ev, "host": host, "keep": (sp, sd, td, out)}, img_handle,
-                stack_handle)
+                map_handle, stack_handle)
 
     def done(self, h):
         return h["ev"].query()
@@ -445,6 +478,7 @@ def make_requests(seed: int, n: int, rate: float, pool: int = 12, scale: float =
                                               h, w, 10, 30)
         sig = sigmas[(h, w, k2)]
         out.append(Request(id=i, t_arrival=t, image_id=key, f=scenes[key], sigma=sig,
+                           sigma_id=("sigma", h, w, k2),
                            kernel="gaussian" if gauss else "box",
                            sigma_s=R / 3.0 if gauss else 0.0, rho=R, N=N))
     return out
@@ -453,8 +487,9 @@ def make_requests(seed: int, n: int, rate: float, pool: int = 12, scale: float =
 def breakdown(reqs, precision="mixed"):
     """Where the saturation rate goes: the same requests' filter calls alone
     (inputs resident, one stream, back to back), their host-device copies
-    alone (image and sigma up, result down, pinned host memory), and the
-    serving loop alone (a CPU executor that finishes every request at once)."""
+    alone (image and sigma up, result down, pinned host memory: what a
+    request moves when nothing it needs is resident), and the serving loop
+    alone (a CPU executor that finishes every request at once)."""
     import torch
     import paper_1811_02308_amd as abf
     dev = torch.device("cuda")
@@ -491,7 +526,7 @@ def breakdown(reqs, precision="mixed"):
         torch.cuda.synchronize()
         res[name + "_mpix_per_s"] = px / (time.perf_counter() - t0) / 1e6
     loop_reqs = [dataclasses.replace(r, t_arrival=0.0) for r in reqs]
-    ex = FakeExecutor(n_slots=4, us_per_px=0.0)
+    ex = FakeExecutor(n_slots=4, us_per_px=0.0, compute=lambda r: None)
     t0 = time.perf_counter()
     Server(ex, 1 << 62, poll_s=0.0).run(loop_reqs, realtime=False)
     res["loop_only_req_per_s"] = len(reqs) / (time.perf_counter() - t0)

@@ -82,6 +82,29 @@ def test_stack_reuse_and_eviction_accounting():
     assert s["ok"] == 30 and s["p99_ms"] >= s["p50_ms"] >= 0
 
 
+def test_sigma_maps_resident_and_counted():
+    """Requests that name their sigma map (sigma_id) upload it once while it
+    stays resident; its bytes count against the budget like images and
+    stacks, and an evicted map is uploaded again."""
+    f = np.zeros((32, 32), np.float32)
+    sg = {k: np.full((32, 32), 10.0 + k, np.float32) for k in range(3)}
+    reqs = [Request(id=i, t_arrival=0.001 * i, image_id=("img", i % 4), f=f, sigma=sg[i % 3],
+                    sigma_id=("sigma", i % 3), N=5) for i in range(30)]
+    ex = FakeExecutor(n_slots=2, us_per_px=1.0)
+    srv = Server(ex, 10**9)
+    res = srv.run(reqs, realtime=False)
+    assert all(r.ok for r in res)
+    assert ex.map_uploads == 3
+    assert srv.maps.bytes == 3 * 4 * 32 * 32
+    # a budget that holds one request's worth: maps are evicted and uploaded again
+    ex2 = FakeExecutor(n_slots=1, us_per_px=1.0)
+    _, map_b, stack_b, tmp_b = ex2.footprint(reqs[0])
+    srv2 = Server(ex2, 4 * 32 * 32 + map_b + stack_b + tmp_b)
+    res2 = srv2.run(reqs, realtime=False)
+    assert all(r.ok for r in res2)
+    assert ex2.map_uploads > 3 and srv2.max_in_use <= srv2.budget
+
+
 def test_request_stream_generator_shapes():
     reqs = make_requests(1004, 12, rate=100.0, scale=1 / 16)
     assert all(r.f.shape[0] in (16, 32, 64, 128) for r in reqs)
@@ -102,6 +125,7 @@ def test_gpu_mix_equals_alone():
                                                             src.rho, src.N, src.sigma_s)
         r.sigma = r.sigma[: r.f.shape[0], : r.f.shape[1]] if r.sigma.shape == r.f.shape else \
             np.full(r.f.shape, 17.0, np.float32)
+        r.sigma_id = ("own", r.id)                     # a map of its own, uploaded once
     srv = Server(GPUExecutor(n_slots=4), 2 << 30)
     res = srv.run(reqs)
     assert all(r.ok for r in res), [r.error for r in res if not r.ok]
