@@ -339,19 +339,18 @@ __device__ __forceinline__ double input_origin(const float* __restrict__ img, lo
 // 1/area). Same steps as legendre_from_moments, with the normalisation
 // folded into the final scaling (the shift is homogeneous in the sums, so
 // it runs on the raw sums with m_0 = area).
+//
+// The conditioning test rho^N <= cond_max, rho = |mid|/half + 1, is taken as
+// |mid| <= dmax half with dmax = cond_max^(1/N) - 1 (computed once per wave).
 template <int N>
 __device__ __forceinline__ bool legendre_from_sums(double (&m)[N + 1], float a, float b,
-                                                   double c, double cond_max, double area,
+                                                   double c, double dmax, double area,
                                                    double inv_area) {
   constexpr LegTable LT{};
   const double mid = 0.5 * ((double)a + (double)b) - c;
   const double half = 0.5 * ((double)b - (double)a);
+  if (!(fabs(mid) <= dmax * half)) return true;
   const double ih = rcp(half);
-  const double rho = fma(fabs(mid), ih, 1.0);
-  double rn = rho;
-#pragma unroll
-  for (int k = 1; k < N; ++k) rn *= rho;
-  if (!(rn <= cond_max)) return true;
   const double s = -mid;
   m[0] = area;
 #pragma unroll
@@ -403,6 +402,8 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
     TS* __restrict__ mom, long long plane, StripGeom g, double cond_max, int vec4, Batch bt,
     FuseArgs fz) {
   __shared__ double sh[kBoxWaves][N][kStripSlots];
+  // shift amplification limit as a bound on |mid - c| / half
+  const double dmax = pow(cond_max, 1.0 / N) - 1.0;
   img += blockIdx.y * bt.img;
   if (FUSED) {
     fz.theta += blockIdx.y * bt.img;
@@ -514,35 +515,51 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
       d[pidx(kV * lane + 3)] = incl;
     }
     wave_sync();
-    // epilogue: lanes take consecutive output columns
-    for (int q = 0; q < kChunks; ++q) {
-      const int j0 = q * kWave;
-      if (j0 >= g.O) break;
-      const int j = j0 + lane;
+    // epilogue: lanes take consecutive output columns, chunk q = columns
+    // 64 q .. 64 q + 63 of the strip's outputs. The chunks have no branch
+    // between them (a flat window's zero moments are selected, and the
+    // ill-conditioned pixels are only marked), so their LDS reads and
+    // arithmetic overlap; the marked pixels are recomputed afterwards.
+    unsigned badq = 0;                   // bit q: this lane's chunk-q pixel is marked
+    auto chunk = [&](int q) {
+      const int j = q * kWave + lane;
       const bool valid = j < g.O && xo + j < W;
       const int x = valid ? xo + j : xo;
       const int e = g.Rpad + (valid ? j : 0);
       const float a = q == 0 ? pa[0] : q == 1 ? pa[1] : q == 2 ? pa[2] : pa[3];
       const float b = q == 0 ? pb[0] : q == 1 ? pb[1] : q == 2 ? pb[2] : pb[3];
-      const long long idx = (long long)y * sp + x;
-      bool bad = false;
-      if (valid) {
-        double m[N + 1];
-        const int eh = e + R, el = e - R - 1;
+      double m[N + 1];
+      const int eh = e + R, el = e - R - 1;
 #pragma unroll
-        for (int k = 0; k < N; ++k) m[k + 1] = shw[k][pidx(eh)] - shw[k][pidx(el)];
-        if (a == b) {
+      for (int k = 0; k < N; ++k) m[k + 1] = shw[k][pidx(eh)] - shw[k][pidx(el)];
+      const bool flat = a == b;
+      const bool bad = legendre_from_sums<N>(m, a, b, c, dmax, area, inv_area) && !flat;
+      if (flat) {
 #pragma unroll
-          for (int k = 1; k <= N; ++k) m[k] = 0.0;
-        } else {
-          bad = legendre_from_sums<N>(m, a, b, c, cond_max, area, inv_area);
-        }
-        if (!bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, idx, mom, plane, fz);
+        for (int k = 1; k <= N; ++k) m[k] = 0.0;
       }
-      const unsigned long long mask = __ballot(valid && bad);
-      if (mask)
-        recompute_flagged<N, TS, FUSED>(mask, valid && bad, y, x, a, b, img, pitch, H, W, R,
-                                        nullptr, inv_area, mom, plane, sp, lane, fz);
+      if (valid && !bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, (long long)y * sp + x, mom,
+                                                    plane, fz);
+      if (valid && bad) badq |= 1u << q;
+    };
+    if (FUSED) {
+      for (int q = 0; q < kChunks; ++q)
+        if (q * kWave < g.O) chunk(q);
+    } else {
+#pragma unroll
+      for (int q = 0; q < kChunks; ++q)
+        if (q * kWave < g.O) chunk(q);
+    }
+    for (int q = 0; q < kChunks; ++q) {
+      const bool mine = (badq >> q) & 1u;
+      const unsigned long long mask = __ballot(mine);
+      if (!mask) continue;
+      const int j = q * kWave + lane;
+      const int x = mine ? xo + j : xo;
+      const float a = q == 0 ? pa[0] : q == 1 ? pa[1] : q == 2 ? pa[2] : pa[3];
+      const float b = q == 0 ? pb[0] : q == 1 ? pb[1] : q == 2 ? pb[2] : pb[3];
+      recompute_flagged<N, TS, FUSED>(mask, mine, y, x, a, b, img, pitch, H, W, R, nullptr,
+                                      inv_area, mom, plane, sp, lane, fz);
     }
     wave_sync();
   }
