@@ -251,6 +251,9 @@ def main():
     ap.add_argument("--precision-table", action="store_true",
                     help="the 4096 x 4096 Voronoi precision sweep (box rho 5 and 20, N = 5..8): "
                          "mixed vs FP64 error per N instead of the headline")
+    ap.add_argument("--kernel-sweep", action="store_true",
+                    help="Gaussian tile kernel (O(rho) per pixel) vs the recursive kernel (O(1)) on a "
+                         "4096 x 4096 field, N = 6, mixed, rho = 8..96, instead of the headline")
     ap.add_argument("--serving-requests", type=int, default=400,
                     help="requests per offered load of the serving stream (p50/p99 at 3 loads); 0 skips it")
     args = ap.parse_args()
@@ -267,6 +270,8 @@ def main():
     cpu, par_px, par_ref = None, None, None
     if args.precision_table:
         return precision_table(args)
+    if args.kernel_sweep:
+        return kernel_sweep(args)
     if not (args.workload.startswith("texture") or args.classical or args.paper_maps):
         wl = workload(args.workload)
         if not args.no_cpu_baseline:
@@ -561,6 +566,76 @@ def precision_table(args):
             rows.append(row)
     print(json.dumps({"metric": "precision sweep, mixed vs FP64 error per N",
                       "config": {"workload": "voronoi4096 box rho 5/20, N 5..8 (one fast-filter call, one stream)"},
+                      "rows": rows}), flush=True)
+
+
+def kernel_sweep(args):
+    """Where the recursive spatial kernel (cost independent of rho) would
+    overtake the Gaussian tile kernel (cost linear in rho per axis): a
+    4096 x 4096 smooth Gaussian field, N = 6, mixed path, one stream, rho in
+    {8, 15, 25, 40, 60, 96}. Per rho: the median event-timed moment-stack
+    call of each kernel and of the whole fast filter, the largest
+    |recursive - Gaussian| output difference over every pixel (the two
+    kernels' weights differ by Deriche's approximation error), and the
+    recursive output's largest error against the CPU oracle on sampled
+    pixels."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1811_02308_amd as abf
+    from synth import gauss_field, smooth_field
+
+    torch.cuda.set_device(0)
+    abf.lib()
+    H = W = 4096
+    N = 6
+    f = gauss_field(1002, H, W)
+    sg = smooth_field(np.random.default_rng(1), H, W, 5, 60)
+    fd, sd = torch.from_numpy(f).cuda(), torch.from_numpy(sg).cuda()
+    reps = max(5, min(args.steps, 10))
+
+    def timed(call):
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            call()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    rng = np.random.default_rng(5)
+    ys = np.concatenate([[0, 0, H - 1, H - 1], rng.integers(0, H, 60)])
+    xs = np.concatenate([[0, W - 1, 0, W - 1], rng.integers(0, W, 60)])
+    rows = []
+    for R in (8, 15, 25, 40, 60, 96):
+        row = {"rho": R, "N": N}
+        outs = {}
+        for kern in ("gaussian", "recursive"):
+            st = torch.empty(abf.stack_bytes(H, W, N, "mixed"), dtype=torch.uint8, device="cuda")
+            ws = torch.empty(abf.lib().abf_kernel_scratch_bytes(H, W, R, N, abf.KERNELS[kern]),
+                             dtype=torch.uint8, device="cuda")
+            wsf = torch.empty(abf.workspace_bytes(H, W, R, N, "mixed", kernel=kern), dtype=torch.uint8,
+                              device="cuda")
+            out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+            row[f"{kern}_stack_ms"] = round(timed(lambda: abf.moment_stack(
+                fd, kernel=kern, rho=R, N=N, precision="mixed", stack=st, workspace=ws)), 4)
+            row[f"{kern}_fast_ms"] = round(timed(lambda: abf.fast(
+                fd, sd, kernel=kern, rho=R, N=N, precision="mixed", out=out, workspace=wsf)), 4)
+            outs[kern] = out.double().cpu().numpy()
+        row["max_abs_recursive_minus_gaussian"] = float(np.max(np.abs(outs["recursive"] - outs["gaussian"])))
+        ref = oracle.fast_abf(f, None, sg, "recursive", R, N, pixels=(ys, xs))
+        row["recursive_max_abs_err_vs_oracle"] = float(np.max(np.abs(outs["recursive"][ys, xs] - ref)))
+        row["oracle_pixels"] = int(len(ys))
+        log(row)
+        rows.append(row)
+    print(json.dumps({"metric": "moment-stack ms, Gaussian tile vs recursive kernel",
+                      "config": {"workload": "gauss_field 4096x4096, N 6, mixed, rho 8..96 (one stream)"},
                       "rows": rows}), flush=True)
 
 

@@ -55,7 +55,22 @@ typedef enum {
     ABF_E_WORKSPACE = -5     /* workspace/stack too small or misaligned     */
 } abf_status;
 
-enum { ABF_KERNEL_BOX = 0, ABF_KERNEL_GAUSSIAN = 1 };
+/* ABF_KERNEL_RECURSIVE: the recursive approximation of the Gaussian that
+ * Sec. II-D names as the O(1)-per-pixel option for the convolutions of
+ * Algorithm 1 -- Deriche's fourth-order sum of two damped complex
+ * exponentials (sigma_s as for the Gaussian, <= 0 meaning rho/3), taken on
+ * the window [-rho, rho] only and normalised to sum 1 per axis, so that
+ * every weight lies inside the window of the bounds. Its moments cost O(1)
+ * per pixel for any rho (truncated first-order recursions along rows and
+ * columns). Taken by abf_fast and abf_moment_stack only, with the workspace
+ * of abf_kernel_workspace_bytes / abf_kernel_scratch_bytes, on the mixed
+ * path only: the passes run along whole rows and columns, so the power
+ * sums share one origin for the image, and under the FP64 path's
+ * conditioning limits the windows far from it (recomputed directly, O(rho^2)
+ * each) made a 4096 x 4096 call take seconds; ABF_PREC_FP64 returns
+ * ABF_E_UNSUPPORTED. Every other entry point taking kernel_kind returns
+ * ABF_E_INVALID for it. */
+enum { ABF_KERNEL_BOX = 0, ABF_KERNEL_GAUSSIAN = 1, ABF_KERNEL_RECURSIVE = 2 };
 enum { ABF_PREC_FP64 = 0, ABF_PREC_MIXED = 1 };
 /* ABF_FLAG_CLAMP: clip the output to [alpha_i, beta_i] (the fitted
  * polynomial may go negative, Sec. II-B); recommended, used by tests.     */
@@ -94,6 +109,12 @@ size_t abf_stack_plane_offset(int h, int w, int N, int precision, int plane);
  * stack (bytes). abf_fast's workspace = abf_stack_bytes + this. */
 size_t abf_scratch_bytes(int h, int w, int rho);
 size_t abf_workspace_bytes(int h, int w, int rho, int N, int precision);
+/* The same for a given spatial kernel: equal to the two above for the box
+ * and Gaussian kernels; for ABF_KERNEL_RECURSIVE the scratch also holds
+ * 2N FP64 planes of h x w (the row pass's sums and the column pass's causal
+ * half) plus the origin and the kernel's weights. */
+size_t abf_kernel_scratch_bytes(int h, int w, int rho, int N, int kernel_kind);
+size_t abf_kernel_workspace_bytes(int h, int w, int rho, int N, int precision, int kernel_kind);
 
 /*
  * abf_minmax -- eq. (bounds): alpha_i / beta_i = min / max of f over the

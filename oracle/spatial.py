@@ -24,9 +24,12 @@ def canon(a: np.ndarray) -> np.ndarray:
 def spatial_weights_1d(kind: str, R: int, sigma_s: float | None = None) -> np.ndarray:
     """1-D factor of the separable spatial kernel on [-R, R], normalised.
 
-    box:      constant (the paper allows any spatial kernel, Sec. I and V).
-    gaussian: exp(-j^2 / (2 sigma_s^2)), eq. (sp_kernel), sigma_s = R/3 by
-              default.
+    box:       constant (the paper allows any spatial kernel, Sec. I and V).
+    gaussian:  exp(-j^2 / (2 sigma_s^2)), eq. (sp_kernel), sigma_s = R/3 by
+               default.
+    recursive: Deriche's sum-of-exponentials approximation of that Gaussian
+               (Sec. II-D's recursive option), truncated to [-R, R]
+               (oracle.recursive).
     """
     j = np.arange(-R, R + 1, dtype=np.float64)
     if kind == "box":
@@ -34,6 +37,11 @@ def spatial_weights_1d(kind: str, R: int, sigma_s: float | None = None) -> np.nd
     elif kind == "gaussian":
         s = (R / 3.0) if (sigma_s is None or sigma_s <= 0) else float(sigma_s)
         w = np.exp(-(j * j) / (2.0 * s * s))
+    elif kind == "recursive":
+        # Deriche's recursive approximation of the Gaussian, truncated to the
+        # window (oracle.recursive); sigma_s as for the Gaussian
+        from .recursive import deriche_weights_1d
+        return deriche_weights_1d(R, sigma_s)
     else:
         raise ValueError(kind)
     return w / w.sum()

@@ -24,7 +24,7 @@ __all__ = [
     "stack_planes", "stack_kernel", "Request", "KERNELS", "PRECISIONS", "ABFError",
 ]
 
-KERNELS = {"box": 0, "gaussian": 1}
+KERNELS = {"box": 0, "gaussian": 1, "recursive": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FLAG_CLAMP = 1
 FLAG_KEEP_STACK = 2
@@ -72,6 +72,8 @@ def lib():
         "abf_stack_plane_offset": ([i, i, i, i, i], sz),
         "abf_scratch_bytes": ([i, i, i], sz),
         "abf_workspace_bytes": ([i, i, i, i, i], sz),
+        "abf_kernel_scratch_bytes": ([i, i, i, i, i], sz),
+        "abf_kernel_workspace_bytes": ([i, i, i, i, i, i], sz),
         "abf_minmax": ([vp, i, i, ll, i, vp, vp, ll, vp, sz, vp], i),
         "abf_moment_stack": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp, sz, vp], i),
         "abf_stack_single_pass": ([i, i, i, i, i], i),
@@ -185,8 +187,8 @@ def _out_dtype(p):
     return torch.float64 if p == 0 else torch.float32
 
 
-def workspace_bytes(h, w, rho, N, precision="mixed"):
-    return int(lib().abf_workspace_bytes(h, w, rho, N, _prec(precision)))
+def workspace_bytes(h, w, rho, N, precision="mixed", kernel="box"):
+    return int(lib().abf_kernel_workspace_bytes(h, w, rho, N, _prec(precision), _kind(kernel)))
 
 
 def stack_bytes(h, w, N, precision="mixed"):
@@ -204,7 +206,7 @@ def fast(img, sigma, theta=None, kernel="box", rho=3, N=5, sigma_s=0.0, precisio
     p = _prec(precision)
     if out is None:
         out = _empty((h, w), _out_dtype(p), img.device, stream)
-    need = lib().abf_workspace_bytes(h, w, rho, N, p)
+    need = lib().abf_kernel_workspace_bytes(h, w, rho, N, p, _kind(kernel))
     if workspace is None:
         workspace = _alloc_bytes(need, img.device, stream)
     st = lib().abf_fast(_ptr(img), _ptr(theta), _ptr(sigma), h, w, pitch, _kind(kernel),
@@ -253,7 +255,8 @@ def moment_stack(img, kernel="box", rho=3, N=5, sigma_s=0.0, precision="mixed", 
     if stack is None:
         stack = _alloc_bytes(lib().abf_stack_bytes(h, w, N, p), img.device, stream)
     if workspace is None:
-        workspace = _alloc_bytes(lib().abf_scratch_bytes(h, w, rho), img.device, stream)
+        workspace = _alloc_bytes(lib().abf_kernel_scratch_bytes(h, w, rho, N, _kind(kernel)),
+                                 img.device, stream)
     st = lib().abf_moment_stack(_ptr(img), h, w, img.stride(0), _kind(kernel), float(sigma_s),
                                 int(rho), int(N), p, _ptr(stack), stack.numel(), _ptr(workspace),
                                 workspace.numel(), _stream(stream))

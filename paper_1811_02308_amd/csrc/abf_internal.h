@@ -134,6 +134,15 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           bool bounds = false);
 
 bool moments_fusable(int kernel_kind, int rho, int N, long long h, long long w);
+
+// Moment planes for the recursive approximation of the Gaussian (kernel kind
+// 2): the alpha/beta planes must hold the window bounds; `scratch` (device,
+// 256-byte aligned) >= recursive_scratch_bytes(h, w, N).
+hipError_t launch_recursive_moments(const float* img, long long pitch, int h, int w,
+                                   double sigma_s, int rho, int N, int prec, const float* alpha,
+                                   const float* beta, long long sp, void* mom,
+                                   long long plane_elems, void* scratch, hipStream_t stream);
+size_t recursive_scratch_bytes(int h, int w, int N);
 // Which moment kernel builds the stack (values of abf_stack_kernel); prec 0 =
 // FP64 stack, 1 = FP32; -1 if no kernel covers the arguments.
 enum { kStackBoundsOnly = 0, kStackBox = 1, kStackTile = 2, kStackTileWide = 3, kStackMfma = 4 };

@@ -68,6 +68,10 @@ size_t elem_bytes(int prec) { return prec == ABF_PREC_FP64 ? 8 : 4; }
 
 bool prec_ok(int p) { return p == ABF_PREC_FP64 || p == ABF_PREC_MIXED; }
 bool kind_ok(int k) { return k == ABF_KERNEL_BOX || k == ABF_KERNEL_GAUSSIAN; }
+// abf_fast and abf_moment_stack also take the recursive kernel
+bool stack_kind_ok(int k) { return kind_ok(k) || k == ABF_KERNEL_RECURSIVE; }
+// the recursive kernel: mixed path only (see abf.h)
+bool rec_supported(int, int precision) { return precision == ABF_PREC_MIXED; }
 
 }  // namespace
 
@@ -114,6 +118,19 @@ size_t abf_workspace_bytes(int h, int w, int rho, int N, int precision) {
   return abf_stack_bytes(h, w, N, precision) + abf_scratch_bytes(h, w, rho);
 }
 
+size_t abf_kernel_scratch_bytes(int h, int w, int rho, int N, int kernel_kind) {
+  if (h < 1 || w < 1 || N < 0 || rho < 0) return 0;
+  const size_t bounds = abf_scratch_bytes(h, w, rho);
+  if (kernel_kind != ABF_KERNEL_RECURSIVE || N == 0) return bounds;
+  const size_t rec = align_up(abf::recursive_scratch_bytes(h, w, N));
+  return rec > bounds ? rec : bounds;
+}
+
+size_t abf_kernel_workspace_bytes(int h, int w, int rho, int N, int precision, int kernel_kind) {
+  if (h < 1 || w < 1 || N < 0) return 0;
+  return abf_stack_bytes(h, w, N, precision) + abf_kernel_scratch_bytes(h, w, rho, N, kernel_kind);
+}
+
 // Window bounds and moment planes of one stack or of a strided batch of
 // stacks (arguments checked by the caller): one launch where the moment
 // kernel takes the bounds as well, else the bounds kernel and then the
@@ -133,6 +150,9 @@ static hipError_t bounds_and_moments(const float* img, int h, int w, long long p
                                sp, mom, sp * h, s, b, nullptr, true);
   hipError_t e = abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, scratch, s, b);
   if (e != hipSuccess || N == 0) return e;
+  if (kernel_kind == ABF_KERNEL_RECURSIVE)   // one image (the caller checks b.n == 1)
+    return abf::launch_recursive_moments(img, pitch, h, w, sigma_s, rho, N, pc, alpha, beta, sp,
+                                         mom, sp * h, scratch, s);
   return abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, pc, alpha, beta, sp,
                              mom, sp * h, s, b);
 }
@@ -188,11 +208,13 @@ abf_status abf_moment_stack(const float* img, int h, int w, long long pitch, int
                             size_t stack_bytes, void* workspace, size_t workspace_bytes,
                             void* stream) {
   if (!img || !stack || !shape_ok(h, w, pitch) || rho < 0 || N < 0 || !prec_ok(precision) ||
-      !kind_ok(kernel_kind) || !std::isfinite(sigma_s))
+      !stack_kind_ok(kernel_kind) || !std::isfinite(sigma_s))
     return ABF_E_INVALID;
   if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (kernel_kind == ABF_KERNEL_RECURSIVE && !rec_supported(N, precision)) return ABF_E_UNSUPPORTED;
   if (!aligned(stack) || stack_bytes < abf_stack_bytes(h, w, N, precision)) return ABF_E_WORKSPACE;
-  if (!workspace || !aligned(workspace) || workspace_bytes < abf_scratch_bytes(h, w, rho))
+  if (!workspace || !aligned(workspace) ||
+      workspace_bytes < abf_kernel_scratch_bytes(h, w, rho, N, kernel_kind))
     return ABF_E_WORKSPACE;
   return hip_status(bounds_and_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N, precision,
                                        static_cast<char*>(stack), workspace,
@@ -287,11 +309,12 @@ abf_status abf_fast(const float* img, const float* theta, const float* sigma, in
                     int precision, unsigned flags, void* out, long long out_pitch,
                     void* workspace, size_t workspace_bytes, void* stream) {
   if (!img || !sigma || !out || !shape_ok(h, w, pitch) || out_pitch < w || rho < 0 || N < 0 ||
-      !prec_ok(precision) || !kind_ok(kernel_kind) || !std::isfinite(sigma_s))
+      !prec_ok(precision) || !stack_kind_ok(kernel_kind) || !std::isfinite(sigma_s))
     return ABF_E_INVALID;
   if (N > ABF_N_MAX || rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+  if (kernel_kind == ABF_KERNEL_RECURSIVE && !rec_supported(N, precision)) return ABF_E_UNSUPPORTED;
   if (!workspace || !aligned(workspace) ||
-      workspace_bytes < abf_workspace_bytes(h, w, rho, N, precision))
+      workspace_bytes < abf_kernel_workspace_bytes(h, w, rho, N, precision, kernel_kind))
     return ABF_E_WORKSPACE;
   const size_t sb = abf_stack_bytes(h, w, N, precision);
   char* ws = static_cast<char*>(workspace);

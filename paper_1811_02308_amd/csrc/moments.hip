@@ -33,6 +33,9 @@
 // (O(R) per pixel), at least 64 output columns wide for every radius up to
 // ABF_RHO_MAX. With unit weights it also serves the FP64 box path at
 // N >= 7, where the box kernel's running sums are not accurate enough.
+#include <cmath>
+#include <complex>
+
 #include "abf_internal.h"
 #include "range_eval.h"
 
@@ -562,6 +565,247 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
                                       inv_area, mom, plane, sp, lane, fz);
     }
     wave_sync();
+  }
+}
+
+// ------------------------------------------------------------ recursive kernel
+// Moments for the recursive approximation of the Gaussian (Sec. II-D names
+// recursive filters, Deriche's and Young and van Vliet's, as a way to make the
+// convolutions of Algorithm 1 cost O(1) per pixel for any width): Deriche's
+// fourth-order sum of two damped complex exponentials, g(t) = Re sum_m A_m
+// z_m^|t| (constants in rec_const), taken on the window j in [-R, R] only,
+// so that every weight lies inside the (2R+1)^2 window of alpha_i, beta_i.
+// Per axis, sum_{|j|<=R} g(j) u(x-j) = Re sum_m A_m (q_m(x) + z_m p_m(x)),
+//   causal     q_m(x) = z_m q_m(x-1) + u(x)   - z_m^(R+1) u(x-R-1),
+//   anticausal p_m(x) = z_m p_m(x+1) + u(x+1) - z_m^R     u(x+R+1),
+// the last term removing the sample that leaves the truncated window: O(1)
+// per sample and power. The power sums are taken about one origin c for the
+// image (rec_prep: the mid-range of sampled inputs), since a pass runs along
+// whole rows and columns. rec_rows (a lane per row, a wave per row segment)
+// writes the horizontal sums of (f - c)^k, k = 1..N, as FP64 planes Hk;
+// rec_cols (a lane per column, a wave per column segment) runs the causal
+// vertical recursion down the segment into FP64 planes Ck, then the
+// anticausal one back up, adds the two halves and finishes each pixel with the
+// shift and Legendre change of the other kernels (ill-conditioned pixels,
+// where one origin for the image is far from a narrow window, are recomputed
+// directly from their window with the kernel's weights). A segment starts R
+// samples early (and the anticausal pass R samples late) from a zero state,
+// so every output is the exact truncated sum, whatever the segment length.
+struct RecConst {
+  double zr[2], zi[2];     // poles z_m
+  double ar[2], ai[2];     // A_m
+  double bzr[2], bzi[2];   // A_m z_m (anticausal output)
+  double z1r[2], z1i[2];   // z_m^(R+1)
+  double zRr[2], zRi[2];   // z_m^R
+  double inv_norm2;        // 1 / (sum_{|j|<=R} g(j))^2 (both axes)
+};
+
+// The kernel's normalised 1-D weights g(j) / sum g, j = -R..R, by value.
+struct RecWeights {
+  double v[2 * kRhoMax + 1];
+};
+
+// mid-range of the input on a 64 x 64 grid of samples -> c[0]; the kernel's
+// normalised 1-D weights (for the exact recompute) -> wts[0 .. 2R].
+__global__ __launch_bounds__(256) void rec_prep(const float* __restrict__ img, long long pitch,
+                                                int H, int W, int R, RecWeights w_host,
+                                                double* __restrict__ c, double* __restrict__ wts) {
+  __shared__ float smin[256], smax[256];
+  const FinMinMax fm;
+  float lo = INFINITY, hi = -INFINITY;
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int yy = (int)(((long long)(i >> 6) * (H - 1)) / 63);
+    const int xx = (int)(((long long)(i & 63) * (W - 1)) / 63);
+    const float v = img[(long long)yy * pitch + xx] + 0.0f;
+    lo = fm.min(lo, v);
+    hi = fm.max(hi, v);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smin[threadIdx.x] = fm.min(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fm.max(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c[0] = 0.5 * ((double)smin[0] + (double)smax[0]);
+  for (int j = threadIdx.x; j <= 2 * R; j += 256) wts[j] = w_host.v[j];
+}
+
+constexpr int kRecSeg = 512;   // outputs per row / column segment
+constexpr size_t kRecWtsBytes = ((2 * kRhoMax + 1) * sizeof(double) + 255) / 256 * 256;
+
+template <int N>
+__global__ __launch_bounds__(kWave) void rec_rows(const float* __restrict__ img, long long pitch,
+                                                  int H, int W, int R, RecConst k,
+                                                  const double* __restrict__ cptr,
+                                                  double* __restrict__ hp, long long plane) {
+  const int lane = threadIdx.x;
+  const int y = blockIdx.y * kWave + lane;
+  if (y >= H) return;
+  const int x0 = blockIdx.x * kRecSeg, x1 = min(W, x0 + kRecSeg);
+  const double c = *cptr;
+  const float* row = img + (long long)y * pitch;
+  double* hrow = hp + (long long)y * W;
+  auto powers = [&](int x, double (&p)[N]) {
+    const double u = (double)(row[min(max(x, 0), W - 1)] + 0.0f) - c;
+    double q = u;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      p[i] = q;
+      q *= u;
+    }
+  };
+  double sr[2][N], si[2][N];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < N; ++i) sr[m][i] = si[m][i] = 0.0;
+  for (int x = x0 - R; x < x1; ++x) {           // causal
+    double pin[N], pout[N];
+    powers(x, pin);
+    const bool sub = x > x0;                    // u(x-R-1) was added
+    if (sub) powers(x - R - 1, pout);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double o = 0.0;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        double nr = fma(k.zr[m], sr[m][i], fma(-k.zi[m], si[m][i], pin[i]));
+        double ni = fma(k.zr[m], si[m][i], k.zi[m] * sr[m][i]);
+        if (sub) {
+          nr = fma(-k.z1r[m], pout[i], nr);
+          ni = fma(-k.z1i[m], pout[i], ni);
+        }
+        sr[m][i] = nr;
+        si[m][i] = ni;
+        o = fma(k.ar[m], nr, fma(-k.ai[m], ni, o));
+      }
+      if (x >= x0) hrow[i * plane + x] = o;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < N; ++i) sr[m][i] = si[m][i] = 0.0;
+  for (int x = x1 + R - 2; x >= x0; --x) {      // anticausal
+    double pin[N], pout[N];
+    powers(x + 1, pin);
+    const bool sub = x <= x1 - 2;               // u(x+R+1) was added
+    if (sub) powers(x + R + 1, pout);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double o = 0.0;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        double nr = fma(k.zr[m], sr[m][i], fma(-k.zi[m], si[m][i], pin[i]));
+        double ni = fma(k.zr[m], si[m][i], k.zi[m] * sr[m][i]);
+        if (sub) {
+          nr = fma(-k.zRr[m], pout[i], nr);
+          ni = fma(-k.zRi[m], pout[i], ni);
+        }
+        sr[m][i] = nr;
+        si[m][i] = ni;
+        o = fma(k.bzr[m], nr, fma(-k.bzi[m], ni, o));
+      }
+      if (x < x1) hrow[i * plane + x] += o;
+    }
+  }
+}
+
+template <int N, typename TS>
+__global__ __launch_bounds__(kWave) void rec_cols(
+    const float* __restrict__ img, long long pitch, int H, int W, int R, RecConst k,
+    const double* __restrict__ cptr, const double* __restrict__ wts,
+    const double* __restrict__ hp, double* __restrict__ cp, long long plane,
+    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
+    TS* __restrict__ mom, long long mplane, double cond_max) {
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x * kWave + lane;
+  const bool live = x < W;
+  const int xc = live ? x : W - 1;
+  const int y0 = blockIdx.y * kRecSeg, y1 = min(H, y0 + kRecSeg);
+  const double c = *cptr;
+  auto hv = [&](int y, double (&v)[N]) {
+    const double* p = hp + (long long)min(max(y, 0), H - 1) * W + xc;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = p[i * plane];
+  };
+  double sr[2][N], si[2][N];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < N; ++i) sr[m][i] = si[m][i] = 0.0;
+  for (int y = y0 - R; y < y1; ++y) {           // causal, down
+    double vin[N], vout[N];
+    hv(y, vin);
+    const bool sub = y > y0;
+    if (sub) hv(y - R - 1, vout);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double o = 0.0;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        double nr = fma(k.zr[m], sr[m][i], fma(-k.zi[m], si[m][i], vin[i]));
+        double ni = fma(k.zr[m], si[m][i], k.zi[m] * sr[m][i]);
+        if (sub) {
+          nr = fma(-k.z1r[m], vout[i], nr);
+          ni = fma(-k.z1i[m], vout[i], ni);
+        }
+        sr[m][i] = nr;
+        si[m][i] = ni;
+        o = fma(k.ar[m], nr, fma(-k.ai[m], ni, o));
+      }
+      if (y >= y0 && live) cp[(long long)i * plane + (long long)y * W + x] = o;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < N; ++i) sr[m][i] = si[m][i] = 0.0;
+  for (int y = y1 + R - 2; y >= y0; --y) {      // anticausal, up, then each pixel
+    double vin[N], vout[N];
+    hv(y + 1, vin);
+    const bool sub = y <= y1 - 2;
+    if (sub) hv(y + R + 1, vout);
+    double m_[N + 1];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double o = 0.0;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        double nr = fma(k.zr[m], sr[m][i], fma(-k.zi[m], si[m][i], vin[i]));
+        double ni = fma(k.zr[m], si[m][i], k.zi[m] * sr[m][i]);
+        if (sub) {
+          nr = fma(-k.zRr[m], vout[i], nr);
+          ni = fma(-k.zRi[m], vout[i], ni);
+        }
+        sr[m][i] = nr;
+        si[m][i] = ni;
+        o = fma(k.bzr[m], nr, fma(-k.bzi[m], ni, o));
+      }
+      m_[i + 1] = o;
+    }
+    if (y >= y1) continue;
+    bool bad = false;
+    float a = 0.f, b = 0.f;
+    if (live) {
+      const long long idx = (long long)y * sp + x;
+      a = alpha[idx];
+      b = beta[idx];
+      m_[0] = 1.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        m_[i + 1] = (m_[i + 1] + cp[(long long)i * plane + (long long)y * W + x]) * k.inv_norm2;
+      bad = legendre_from_moments<N>(m_, a, b, c, cond_max);
+      if (!bad) finish_pixel<N, TS, false>(m_, a, b, y, x, idx, mom, mplane, FuseArgs{});
+    }
+    const unsigned long long mask = __ballot(live && bad);
+    if (mask)
+      recompute_flagged<N, TS, false>(mask, live && bad, y, x, a, b, img, pitch, H, W, R, wts, 1.0,
+                                      mom, mplane, sp, lane, FuseArgs{});
   }
 }
 
@@ -1266,8 +1510,9 @@ int device_cus() {
 constexpr double fp64_cond_max(int N) { return N <= 5 ? 1e8 : (N == 6 ? 1e6 : 1e4); }
 
 // The matrix-core kernel is the faster one for wide windows on large
-// images (measured: at 2048^2 and 4096^2 with 8 <= R <= 16 it takes 0.8-0.95
-// of the tile kernel's time; at 1024^2 they tie, below that it is slower).
+// images on the mixed path (measured: at 2048^2 and 4096^2 with 8 <= R <= 16
+// it takes 0.8-0.95 of the tile kernel's time; at 1024^2 they tie, below
+// that it is slower); the FP64 path keeps the tile kernel.
 // Degrees 7 and 8 stay on the tile kernel, whose re-origin passes keep
 // their ill-conditioned pixels cheap.
 bool gauss_on_mfma(int R, int N, long long h, long long w) {
@@ -1330,7 +1575,13 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     return hipGetLastError();
   }
   const double s = sigma_s > 0 ? sigma_s : (R > 0 ? R / 3.0 : 1.0);
-  if (!fs && !box_tile && gauss_on_mfma(R, N, h, w)) {
+  // (the FP64 path takes the tile kernel there instead, reading the bounds:
+  // the matrix-core kernel takes one origin per 16-column strip segment,
+  // and under the FP64 path's tighter conditioning limits the pixels it
+  // recomputed from their windows cost 13-40 ms per 4096^2 image at
+  // R = 8-15, N = 6, on a field with wide flat regions, against about 1 ms
+  // for the tile kernel, whose origin is local to a 4-row tile)
+  if (!fs && !box_tile && sizeof(TS) == 4 && gauss_on_mfma(R, N, h, w)) {
     // strips of 16 columns; segment height a multiple of 16, chosen so the
     // grid has about two waves per SIMD (8 per CU)
     const int n_strips = (w + 15) / 16;
@@ -1375,6 +1626,84 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   return hipErrorInvalidValue;
 }
 
+// Deriche's constants for the Gaussian (order 0), scaled by sigma_s: poles
+// z_m = exp(-(b_m - i w_m) / s), weights A_m = a_m - i a'_m.
+constexpr double kDerA[2] = {1.680, -0.6803}, kDerAp[2] = {3.735, -0.2598};
+constexpr double kDerB[2] = {1.783, 1.723}, kDerW[2] = {0.6318, 1.997};
+
+double rec_sigma(int R, double sigma_s) {
+  const double s = sigma_s > 0 ? sigma_s : R / 3.0;
+  return s > 0 ? s : 1.0;
+}
+
+void rec_setup(int R, double sigma_s, RecConst& k, RecWeights& wt) {
+  const double s = rec_sigma(R, sigma_s);
+  double norm = 0.0;
+  for (int j = -R; j <= R; ++j) {
+    double g = 0.0;
+    for (int m = 0; m < 2; ++m) {
+      const double t = std::fabs((double)j) / s;
+      g += (kDerA[m] * std::cos(kDerW[m] * t) + kDerAp[m] * std::sin(kDerW[m] * t)) *
+           std::exp(-kDerB[m] * t);
+    }
+    wt.v[j + R] = g;
+    norm += g;
+  }
+  for (int j = 0; j <= 2 * R; ++j) wt.v[j] /= norm;
+  for (int m = 0; m < 2; ++m) {
+    const std::complex<double> z = std::exp(std::complex<double>(-kDerB[m], kDerW[m]) / s);
+    const std::complex<double> A(kDerA[m], -kDerAp[m]);
+    const std::complex<double> bz = A * z, z1 = std::pow(z, R + 1), zR = std::pow(z, R);
+    k.zr[m] = z.real();
+    k.zi[m] = z.imag();
+    k.ar[m] = A.real();
+    k.ai[m] = A.imag();
+    k.bzr[m] = bz.real();
+    k.bzi[m] = bz.imag();
+    k.z1r[m] = z1.real();
+    k.z1i[m] = z1.imag();
+    k.zRr[m] = zR.real();
+    k.zRi[m] = zR.imag();
+  }
+  k.inv_norm2 = 1.0 / (norm * norm);
+}
+
+template <int N, typename TS>
+hipError_t launch_rec_t(const float* img, long long pitch, int h, int w, double sigma_s, int R,
+                        const float* alpha, const float* beta, long long sp, TS* mom,
+                        long long plane, void* scratch, hipStream_t stream) {
+  RecConst k;
+  RecWeights wt;
+  rec_setup(R, sigma_s, k, wt);
+  char* base = static_cast<char*>(scratch);
+  double* c = reinterpret_cast<double*>(base);
+  double* wts = reinterpret_cast<double*>(base + 256);
+  double* hp = reinterpret_cast<double*>(base + 256 + kRecWtsBytes);
+  double* cp = hp + (long long)N * h * w;
+  const long long hplane = (long long)h * w;
+  const double cond_max = sizeof(TS) == 4 ? 1e12 : fp64_cond_max(N);
+  hipLaunchKernelGGL(rec_prep, dim3(1), dim3(256), 0, stream, img, pitch, h, w, R, wt, c, wts);
+  hipLaunchKernelGGL((rec_rows<N>), dim3((w + kRecSeg - 1) / kRecSeg, (h + kWave - 1) / kWave),
+                     dim3(kWave), 0, stream, img, pitch, h, w, R, k, c, hp, hplane);
+  hipLaunchKernelGGL((rec_cols<N, TS>), dim3((w + kWave - 1) / kWave, (h + kRecSeg - 1) / kRecSeg),
+                     dim3(kWave), 0, stream, img, pitch, h, w, R, k, c, wts, hp, cp, hplane, alpha,
+                     beta, sp, mom, plane, cond_max);
+  return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t dispatch_rec(int N, const float* img, long long pitch, int h, int w, double sigma_s,
+                        int R, const float* alpha, const float* beta, long long sp, TS* mom,
+                        long long plane, void* scratch, hipStream_t stream) {
+  switch (N) {
+#define ABF_CASE(n) \
+  case n: return launch_rec_t<n, TS>(img, pitch, h, w, sigma_s, R, alpha, beta, sp, mom, plane, scratch, stream);
+    ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6) ABF_CASE(7) ABF_CASE(8)
+#undef ABF_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename TS>
 hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, int kind,
                       double sigma_s, int R, float* alpha, float* beta,
@@ -1403,6 +1732,22 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                            static_cast<float*>(mom), plane_elems, stream, b, fuse, bounds);
 }
 
+hipError_t launch_recursive_moments(const float* img, long long pitch, int h, int w,
+                                   double sigma_s, int rho, int N, int prec, const float* alpha,
+                                   const float* beta, long long sp, void* mom,
+                                   long long plane_elems, void* scratch, hipStream_t stream) {
+  if (N < 1 || N > kNMax || rho < 0 || rho > kRhoMax) return hipErrorInvalidValue;
+  if (prec == 0)
+    return dispatch_rec<double>(N, img, pitch, h, w, sigma_s, rho, alpha, beta, sp,
+                                static_cast<double*>(mom), plane_elems, scratch, stream);
+  return dispatch_rec<float>(N, img, pitch, h, w, sigma_s, rho, alpha, beta, sp,
+                             static_cast<float*>(mom), plane_elems, scratch, stream);
+}
+
+size_t recursive_scratch_bytes(int h, int w, int N) {
+  return 256 + kRecWtsBytes + (size_t)2 * N * (size_t)h * (size_t)w * sizeof(double);
+}
+
 bool moments_take_bounds(int kernel_kind, int rho, int N, long long h, long long w) {
   // the Gaussian tile kernel (its LDS, the power sums and the (min, max)
   // pairs, (N + 1) kTY ES 8 bytes, plus the weights, is at most 74 KiB, so
@@ -1419,7 +1764,7 @@ int stack_kernel_id(int kernel_kind, int rho, int N, int prec, long long h, long
   // the FP64 box path at N >= 7 takes the tile kernel with unit weights
   const bool box_tile = kernel_kind == 0 && prec == 0 && N >= 7;
   if (kernel_kind == 0 && !box_tile) return kStackBox;
-  if (!box_tile && gauss_on_mfma(rho, N, h, w)) return kStackMfma;
+  if (!box_tile && prec == 1 && gauss_on_mfma(rho, N, h, w)) return kStackMfma;
   const int tx = gauss_tile_tx(rho, N);
   if (tx <= 0) return -1;
   return tx + 2 * rho <= kESNarrow ? kStackTile : kStackTileWide;

@@ -336,6 +336,11 @@ class GPUExecutor:
         self.precision = precision
         self.dev = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
+        # uploads of inputs that stay resident (images, sigma maps with an
+        # identity) go on their own stream, so that a request on another slot
+        # that reuses them waits for the copy only, not for the compute queued
+        # on the uploading request's slot
+        self.copy_stream = torch.cuda.Stream(device=self.dev)
         self.free_slots = list(range(n_slots))
         # pinned staging copies of host arrays reused across requests, LRU by
         # bytes (a dropped copy stays valid for copies already enqueued: torch's
@@ -382,15 +387,19 @@ class GPUExecutor:
         s = self.streams[slot]
         h, w = r.shape
         p = abf.PRECISIONS[self.precision]
+        def resident_upload(a):
+            with torch.cuda.stream(self.copy_stream):
+                d = self._pin(a).to(self.dev, non_blocking=True)
+                ev_up = torch.cuda.Event()
+                ev_up.record(self.copy_stream)
+            return d, ev_up
+
+        if img_handle is None:
+            img_handle = resident_upload(r.f)
+        if map_handle is None and r.sigma_id is not None:
+            map_handle = resident_upload(r.sigma)
         with torch.cuda.stream(s):
-            if img_handle is None:
-                pin = self._pin(r.f)
-                fd = pin.to(self.dev, non_blocking=True)
-                ev_img = torch.cuda.Event()
-                ev_img.record(s)
-                img_handle = (fd, ev_img)
-            else:
-                s.wait_event(img_handle[1])
+            s.wait_event(img_handle[1])
             fd = img_handle[0]
             td = None
             if r.theta is not None:
@@ -402,10 +411,6 @@ class GPUExecutor:
             else:
                 sp = self._pin(r.sigma)
                 sd = sp.to(self.dev, non_blocking=True)
-                if r.sigma_id is not None:
-                    ev_map = torch.cuda.Event()
-                    ev_map.record(s)
-                    map_handle = (sd, ev_map)
             out = torch.empty((h, w), dtype=torch.float32 if p else torch.float64, device=self.dev)
             if stack_handle is None:
                 stack = torch.empty(int(abf.lib().abf_stack_bytes(h, w, r.N, p)), dtype=torch.uint8,

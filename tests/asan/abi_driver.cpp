@@ -98,6 +98,32 @@ static void entry_points() {
                                     out.p, pitch, nullptr) == ABF_OK);
           }
         }
+  // the recursive kernel: its own workspace size, abf_fast and abf_moment_stack only
+  for (int prec = 0; prec <= 1; ++prec)
+    for (int N : {1, 5, 6, 7})
+      for (int rho : {0, 3, 30}) {
+        const int k = ABF_KERNEL_RECURSIVE;
+        const size_t wsb = abf_kernel_workspace_bytes(h, w, rho, N, prec, k);
+        const size_t sb = abf_stack_bytes(h, w, N, prec);
+        CHECK(wsb > abf_workspace_bytes(h, w, rho, N, prec));
+        CHECK(abf_kernel_workspace_bytes(h, w, rho, N, prec, 0) ==
+              abf_workspace_bytes(h, w, rho, N, prec));
+        Buf ws(wsb), st(sb), scr(abf_kernel_scratch_bytes(h, w, rho, N, k));
+        const abf_status want = prec == ABF_PREC_FP64 ? ABF_E_UNSUPPORTED : ABF_OK;
+        CHECK(abf_fast(img.f(), nullptr, sg.f(), h, w, pitch, k, 0.0, rho, N, prec, 1, out.p,
+                       pitch, ws.p, wsb, nullptr) == want);
+        CHECK(abf_moment_stack(img.f(), h, w, pitch, k, 0.0, rho, N, prec, st.p, sb, scr.p,
+                               scr.bytes, nullptr) == want);
+        if (want == ABF_OK) {
+          CHECK(abf_fast(img.f(), nullptr, sg.f(), h, w, pitch, k, 0.0, rho, N, prec, 1, out.p,
+                         pitch, ws.p, abf_workspace_bytes(h, w, rho, N, prec),
+                         nullptr) == ABF_E_WORKSPACE);
+        }
+        CHECK(abf_stack_moments(img.f(), h, w, pitch, k, 0.0, rho, N, prec, st.p, sb, nullptr) ==
+              ABF_E_INVALID);
+        CHECK(abf_bruteforce(img.f(), nullptr, sg.f(), h, w, pitch, k, 0.0, rho, prec, out.p,
+                             pitch, nullptr) == ABF_E_INVALID);
+      }
   const size_t wsb = abf_workspace_bytes(h, w, 3, 5, ABF_PREC_MIXED);
   Buf ws(wsb);
   // invalid arguments: refused before any launch
@@ -108,7 +134,7 @@ static void entry_points() {
                  wsb, nullptr) == ABF_E_INVALID);
   CHECK(abf_fast(img.f(), nullptr, sg.f(), h, w, w - 1, 0, 0.0, 3, 5, 1, 1, out.p, pitch, ws.p,
                  wsb, nullptr) == ABF_E_INVALID);
-  CHECK(abf_fast(img.f(), nullptr, sg.f(), h, w, pitch, 2, 0.0, 3, 5, 1, 1, out.p, pitch, ws.p,
+  CHECK(abf_fast(img.f(), nullptr, sg.f(), h, w, pitch, 3, 0.0, 3, 5, 1, 1, out.p, pitch, ws.p,
                  wsb, nullptr) == ABF_E_INVALID);
   CHECK(abf_fast(img.f(), nullptr, sg.f(), h, w, pitch, 0, 0.0, -1, 5, 1, 1, out.p, pitch, ws.p,
                  wsb, nullptr) == ABF_E_INVALID);

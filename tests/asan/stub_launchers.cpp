@@ -84,6 +84,26 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w, int, 
   return hipSuccess;
 }
 
+hipError_t launch_recursive_moments(const float* img, long long pitch, int h, int w, double, int,
+                                   int N, int prec, const float* alpha, const float* beta,
+                                   long long sp, void* mom, long long plane_elems, void* scratch,
+                                   hipStream_t) {
+  ++g_calls;
+  const size_t e = prec == 0 ? 8 : 4;
+  plane(img, pitch, h, w, 4, 1, 0, "recursive img");
+  plane(alpha, sp, h, w, 4, 1, 0, "recursive alpha");
+  plane(beta, sp, h, w, 4, 1, 0, "recursive beta");
+  for (int k = 0; k < N; ++k)
+    plane(static_cast<const char*>(mom) + (size_t)k * plane_elems * e, sp, h, w, e, 1, 0,
+          "recursive plane");
+  need(scratch, recursive_scratch_bytes(h, w, N), "recursive scratch");
+  return hipSuccess;
+}
+
+size_t recursive_scratch_bytes(int h, int w, int N) {
+  return 256 + 1792 + (size_t)2 * N * (size_t)h * (size_t)w * sizeof(double);
+}
+
 bool moments_fusable(int kernel_kind, int rho, int N, long long, long long) {
   return N >= 1 && N <= 8 && (kernel_kind == 0 || rho <= 40);
 }

@@ -132,7 +132,7 @@ def test_stack_kernel_query():
     assert L.abf_stack_kernel(4096, 4096, 0, 40, 8, 0) == WIDE
     assert L.abf_stack_kernel(1024, 1024, 1, 15, 6, 1) == TILE
     assert L.abf_stack_kernel(2048, 2048, 1, 15, 6, 1) == MFMA
-    assert L.abf_stack_kernel(2048, 2048, 1, 15, 6, 0) == MFMA
+    assert L.abf_stack_kernel(2048, 2048, 1, 15, 6, 0) == TILE          # FP64 keeps the tile kernel
     assert L.abf_stack_kernel(2048, 2047, 1, 15, 6, 1) == TILE         # below 2^22 pixels
     assert L.abf_stack_kernel(2048, 2048, 1, 15, 7, 1) == TILE         # N = 7 stays on the tile
     assert L.abf_stack_kernel(2048, 2048, 1, 7, 6, 1) == TILE          # R < 8
