@@ -254,6 +254,9 @@ def main():
     ap.add_argument("--kernel-sweep", action="store_true",
                     help="Gaussian tile kernel (O(rho) per pixel) vs the recursive kernel (O(1)) on a "
                          "4096 x 4096 field, N = 6, mixed, rho = 8..96, instead of the headline")
+    ap.add_argument("--batched", action="store_true",
+                    help="abf_fast_batched (one launch per stage per group) against one abf_fast call "
+                         "per request, on small-image, mixed-size and 96-plane batches, instead of the headline")
     ap.add_argument("--serving-requests", type=int, default=400,
                     help="requests per offered load of the serving stream (p50/p99 at 3 loads); 0 skips it")
     args = ap.parse_args()
@@ -272,6 +275,8 @@ def main():
         return precision_table(args)
     if args.kernel_sweep:
         return kernel_sweep(args)
+    if args.batched:
+        return batched_bench(args)
     if not (args.workload.startswith("texture") or args.classical or args.paper_maps):
         wl = workload(args.workload)
         if not args.no_cpu_baseline:
@@ -636,6 +641,118 @@ def kernel_sweep(args):
         rows.append(row)
     print(json.dumps({"metric": "moment-stack ms, Gaussian tile vs recursive kernel",
                       "config": {"workload": "gauss_field 4096x4096, N 6, mixed, rho 8..96 (one stream)"},
+                      "rows": rows}), flush=True)
+
+
+def batched_bench(args):
+    """abf_fast_batched against a host loop of abf_fast calls over the same
+    requests (each request in its own allocations, workspace and request
+    table built once, both through the C ABI on one stream, mixed path):
+    64 images of 256 x 256 (one group), a mix of 48 requests of three sizes
+    and two parameter sets (six groups), and the 96 planes of 1920 x 1080 of
+    the texture batch (one group; abf_fast_strided beside it). Per case: the
+    median event-timed device time per call of each route and the outputs'
+    equality."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_1811_02308_amd as abf
+    from synth import rect_scene, smooth_field
+
+    torch.cuda.set_device(0)
+    L = abf.lib()
+    prec = 1
+    reps = max(5, min(args.steps, 20))
+
+    def timed(call):
+        for _ in range(5):
+            call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            call()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    scenes = {}
+
+    def case(name, specs):
+        reqs = (abf.Request * len(specs))()
+        keep, outs_b, outs_l, singles = [], [], [], []
+        for i, (h, w, kernel, R, N) in enumerate(specs):
+            key = (i % 8, h, w)
+            if key not in scenes:
+                scenes[key] = (rect_scene(900 + i % 8, h, w, n_rect=6, noise=8.0, side_lo=4,
+                                          side_hi=max(5, min(h, w) // 2)),
+                               smooth_field(np.random.default_rng(i % 8), h, w, 8, 40))
+            f = torch.from_numpy(scenes[key][0]).cuda()
+            sg = torch.from_numpy(scenes[key][1]).cuda()
+            ob = torch.empty((h, w), dtype=torch.float32, device="cuda")
+            ol = torch.empty_like(ob)
+            ws = torch.empty(abf.workspace_bytes(h, w, R, N, "mixed", kernel=kernel), dtype=torch.uint8,
+                             device="cuda")
+            keep += [f, sg, ws]
+            outs_b.append(ob)
+            outs_l.append(ol)
+            reqs[i] = abf.Request(f.data_ptr(), None, sg.data_ptr(), h, w, w, abf.KERNELS[kernel], 0.0,
+                                  R, N, ob.data_ptr(), w)
+            singles.append((ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(sg.data_ptr()), h, w,
+                            abf.KERNELS[kernel], R, N, ctypes.c_void_p(ol.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        n = len(specs)
+        wsb = L.abf_batched_workspace_bytes(reqs, n, prec)
+        bws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+        def batched():
+            st = L.abf_fast_batched(reqs, n, prec, abf.FLAG_CLAMP, ctypes.c_void_p(bws.data_ptr()), wsb,
+                                    stream)
+            if st != 0:
+                raise RuntimeError(f"abf_fast_batched: {st}")
+
+        def loop():
+            for (fp, sp, h, w, kind, R, N, op, wp, wn) in singles:
+                st = L.abf_fast(fp, None, sp, h, w, w, kind, 0.0, R, N, prec, abf.FLAG_CLAMP, op, w, wp,
+                                wn, stream)
+                if st != 0:
+                    raise RuntimeError(f"abf_fast: {st}")
+
+        row = {"case": name, "requests": n, "groups": len({s for s in specs}),
+               "mpix": round(sum(h * w for h, w, *_ in specs) / 1e6, 3)}
+        row["loop_ms"] = round(timed(loop), 4)
+        row["batched_ms"] = round(timed(batched), 4)
+        row["loop_mpix_s"] = round(row["mpix"] * 1e3 / row["loop_ms"], 1)
+        row["batched_mpix_s"] = round(row["mpix"] * 1e3 / row["batched_ms"], 1)
+        row["speedup"] = round(row["loop_ms"] / row["batched_ms"], 3)
+        torch.cuda.synchronize()
+        row["outputs_equal"] = all(torch.equal(a, b) for a, b in zip(outs_b, outs_l))
+        if name == "texture_planes":
+            h, w, kernel, R, N = specs[0]
+            x = torch.stack([keep[3 * i] for i in range(n)])
+            sgs = torch.stack([keep[3 * i + 1] for i in range(n)])
+            out = torch.empty_like(x)
+            sws = torch.empty(L.abf_strided_workspace_bytes(n, h, w, R, N, prec), dtype=torch.uint8,
+                              device="cuda")
+            row["strided_ms"] = round(timed(lambda: abf.fast_strided(
+                x, sgs, kernel=kernel, rho=R, N=N, precision="mixed", out=out, workspace=sws)), 4)
+        log(row)
+        return row
+
+    rows = [case("small_256", [(256, 256, "box", 5, 6)] * 64)]
+    mix = []
+    for i in range(48):
+        side = (256, 512, 1024)[i % 3]
+        mix.append((side, side, "box", 5, 6) if i % 2 else (side, side * 4 // 3, "gaussian", 3, 5))
+    rows.append(case("mixed_sizes", mix))
+    rows.append(case("texture_planes", [(1080, 1920, "box", 8, 6)] * 96))
+    print(json.dumps({"metric": "ms per batch, abf_fast_batched vs a loop of abf_fast",
+                      "config": {"workload": "batches of independent requests, mixed path, one stream"},
                       "rows": rows}), flush=True)
 
 

@@ -312,9 +312,23 @@ typedef struct abf_request {
 
 /*
  * abf_fast_batched -- abf_fast over n independent requests (images or
- * colour channels of any sizes and parameters) in one call on one stream.
- * workspace >= abf_batched_workspace_bytes(reqs, n, precision); each
- * request's stack and scratch get their own 256-byte aligned slice.
+ * colour channels of any sizes and parameters; kernel_kind box, Gaussian or
+ * recursive, under the same rules as abf_fast) in one call on one stream.
+ * Requests that agree in h, w, pitch, out_pitch, kernel_kind, sigma_s, rho,
+ * N and in whether theta is given form a group (at most 65535 requests; in
+ * order of first appearance) whose images share each stage's launch: a
+ * table of every member's byte offsets from the group's first request (its
+ * image, theta, sigma, output and stack) is written to the workspace, and
+ * each kernel finds its image through it, so each member may live in its
+ * own allocation. A group of one, and every recursive request, runs as
+ * abf_fast. The results are bit-identical to abf_fast on each request.
+ * Pointers of one group must share the alignment of the group's first
+ * (any caller-allocated float32 / float64 planes do).
+ * workspace (device, 256-byte aligned) >= abf_batched_workspace_bytes(reqs,
+ * n, precision): the offset table (40 bytes per request, rounded up to 256),
+ * then one 256-byte aligned slice per request for its stack and scratch.
+ * Validation as abf_fast for every request before any launch; n = 0 returns
+ * ABF_OK without touching the workspace.
  */
 size_t abf_batched_workspace_bytes(const abf_request* reqs, int n, int precision);
 abf_status abf_fast_batched(const abf_request* reqs, int n, int precision,

@@ -74,17 +74,45 @@ struct ShiftedLegTable {
   }
 };
 
-// A batch of images of one shape and one parameter set, laid out at fixed
-// strides: image z uses img + z*img (elements; also theta and sigma), the
-// stack at byte offset z*stack, and out + z*out (elements). Kernels take the
-// image index from the last grid dimension, so a whole batch is one launch
-// per stage. n = 1 with zero strides is a single image.
+// Byte offsets of one image's planes from image 0's: the image, the plane
+// the range stage reads as theta (theta, or the image where theta = f), sigma,
+// the stack, the output.
+struct BatchOffsets {
+  long long img, theta, sigma, stack, out;
+};
+
+// A batch of images of one shape and one parameter set. Kernels take the
+// image index z from the last grid dimension, so a whole batch is one launch
+// per stage. Image z is found either at fixed strides -- img + z*img
+// (elements; also theta and sigma), the stack at byte offset z*stack, out +
+// z*out (elements) -- or, where `tab` is set, at the byte offsets tab[z]
+// (device memory, filled before the launch; `host_tab` is the same table in
+// host memory for launchers that loop over the images on the host). n = 1
+// with zero strides and no table is a single image.
 struct Batch {
   int n = 1;
   long long img = 0;
   long long stack = 0;
   long long out = 0;
+  const BatchOffsets* tab = nullptr;
+  const BatchOffsets* host_tab = nullptr;
+
+  // offsets of image z (out_size: bytes per output element)
+  __device__ __forceinline__ BatchOffsets at(long long z, int out_size) const {
+    if (tab) return tab[z];
+    return BatchOffsets{z * img * 4, z * img * 4, z * img * 4, z * stack, z * out * out_size};
+  }
+  BatchOffsets at_host(long long z, int out_size) const {
+    if (host_tab) return host_tab[z];
+    return BatchOffsets{z * img * 4, z * img * 4, z * img * 4, z * stack, z * out * out_size};
+  }
 };
+
+// Copies n offset records from host memory into `dev` (device, 8-byte
+// aligned) in stream order (the records travel as kernel arguments, so the
+// host array may be freed when this returns).
+hipError_t launch_write_offsets(BatchOffsets* dev, const BatchOffsets* host, int n,
+                                hipStream_t stream);
 
 // p[i] for a wave-uniform base p and a per-lane 32-bit byte offset (the
 // load then takes the base from scalar registers and the offset from one

@@ -4,7 +4,9 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "abf_internal.h"
 
@@ -378,11 +380,28 @@ abf_status abf_bruteforce(const float* img, const float* theta, const float* sig
                                       static_cast<hipStream_t>(stream)));
 }
 
+// Requests that share launches in abf_fast_batched: one shape and pitch,
+// one output pitch, one kernel, radius and degree, theta given by all or by
+// none (the recursive kernel takes one image per launch).
+static bool same_group(const abf_request& a, const abf_request& b) {
+  return a.kernel_kind != ABF_KERNEL_RECURSIVE && a.h == b.h && a.w == b.w &&
+         a.pitch == b.pitch && a.out_pitch == b.out_pitch && a.kernel_kind == b.kernel_kind &&
+         a.rho == b.rho && a.N == b.N &&
+         std::memcmp(&a.sigma_s, &b.sigma_s, sizeof(double)) == 0 && !a.theta == !b.theta;
+}
+
+static long long byte_diff(const void* a, const void* b) {
+  return static_cast<long long>(reinterpret_cast<uintptr_t>(a) - reinterpret_cast<uintptr_t>(b));
+}
+
+static size_t request_bytes(const abf_request& r, int precision) {
+  return align_up(abf_kernel_workspace_bytes(r.h, r.w, r.rho, r.N, precision, r.kernel_kind));
+}
+
 size_t abf_batched_workspace_bytes(const abf_request* reqs, int n, int precision) {
   if (!reqs || n < 0) return 0;
-  size_t tot = 0;
-  for (int i = 0; i < n; ++i)
-    tot += align_up(abf_workspace_bytes(reqs[i].h, reqs[i].w, reqs[i].rho, reqs[i].N, precision));
+  size_t tot = align_up((size_t)n * sizeof(abf::BatchOffsets));
+  for (int i = 0; i < n; ++i) tot += request_bytes(reqs[i], precision);
   return tot;
 }
 
@@ -392,21 +411,77 @@ abf_status abf_fast_batched(const abf_request* reqs, int n, int precision, unsig
   for (int i = 0; i < n; ++i) {
     const abf_request& r = reqs[i];
     if (!r.img || !r.sigma || !r.out || !shape_ok(r.h, r.w, r.pitch) || r.out_pitch < r.w ||
-        r.rho < 0 || r.N < 0 || !kind_ok(r.kernel_kind))
+        r.rho < 0 || r.N < 0 || !stack_kind_ok(r.kernel_kind) || !std::isfinite(r.sigma_s))
       return ABF_E_INVALID;
     if (r.N > ABF_N_MAX || r.rho > ABF_RHO_MAX) return ABF_E_UNSUPPORTED;
+    if (r.kernel_kind == ABF_KERNEL_RECURSIVE && !rec_supported(r.N, precision))
+      return ABF_E_UNSUPPORTED;
   }
-  if (n > 0 && (!workspace || !aligned(workspace) ||
-                workspace_bytes < abf_batched_workspace_bytes(reqs, n, precision)))
+  if (n == 0) return ABF_OK;
+  if (!workspace || !aligned(workspace) ||
+      workspace_bytes < abf_batched_workspace_bytes(reqs, n, precision))
     return ABF_E_WORKSPACE;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // workspace: the offset table, then one slice per request (its stack,
+  // then its scratch)
   char* ws = static_cast<char*>(workspace);
+  abf::BatchOffsets* dev_tab = reinterpret_cast<abf::BatchOffsets*>(ws);
+  char* slices = ws + align_up((size_t)n * sizeof(abf::BatchOffsets));
+  std::vector<size_t> slice(n);
+  for (size_t i = 0, off = 0; i < (size_t)n; off += request_bytes(reqs[i], precision), ++i)
+    slice[i] = off;
+  // groups in order of first appearance (at most 65535 images per launch)
+  std::vector<std::vector<int>> groups;
   for (int i = 0; i < n; ++i) {
-    const abf_request& r = reqs[i];
-    const size_t need = align_up(abf_workspace_bytes(r.h, r.w, r.rho, r.N, precision));
-    abf_status st = abf_fast(r.img, r.theta, r.sigma, r.h, r.w, r.pitch, r.kernel_kind, r.sigma_s,
-                             r.rho, r.N, precision, flags, r.out, r.out_pitch, ws, need, stream);
+    size_t g = 0;
+    while (g < groups.size() &&
+           !(groups[g].size() < 65535 && same_group(reqs[groups[g][0]], reqs[i])))
+      ++g;
+    if (g == groups.size()) groups.emplace_back();
+    groups[g].push_back(i);
+  }
+  // offsets of every member from its group's first, group after group
+  std::vector<abf::BatchOffsets> host(n);
+  std::vector<int> first(groups.size());
+  bool shared = false;
+  for (size_t g = 0, pos = 0; g < groups.size(); ++g) {
+    first[g] = (int)pos;
+    shared = shared || groups[g].size() > 1;
+    const abf_request& r0 = reqs[groups[g][0]];
+    const void* th0 = r0.theta ? static_cast<const void*>(r0.theta) : r0.img;
+    for (int j : groups[g]) {
+      const abf_request& r = reqs[j];
+      const void* th = r.theta ? static_cast<const void*>(r.theta) : r.img;
+      host[pos++] = abf::BatchOffsets{byte_diff(r.img, r0.img), byte_diff(th, th0),
+                                      byte_diff(r.sigma, r0.sigma),
+                                      (long long)(slice[j] - slice[groups[g][0]]),
+                                      byte_diff(r.out, r0.out)};
+    }
+  }
+  if (shared && abf::launch_write_offsets(dev_tab, host.data(), n, s) != hipSuccess)
+    return ABF_E_HIP;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const int i0 = groups[g][0];
+    const abf_request& r = reqs[i0];
+    char* base = slices + slice[i0];
+    if (groups[g].size() == 1) {
+      const abf_status st = abf_fast(r.img, r.theta, r.sigma, r.h, r.w, r.pitch, r.kernel_kind,
+                                     r.sigma_s, r.rho, r.N, precision, flags, r.out, r.out_pitch,
+                                     base, request_bytes(r, precision), stream);
+      if (st != ABF_OK) return st;
+      continue;
+    }
+    abf::Batch b;
+    b.n = (int)groups[g].size();
+    b.tab = dev_tab + first[g];
+    b.host_tab = host.data() + first[g];
+    const hipError_t e =
+        bounds_and_moments(r.img, r.h, r.w, r.pitch, r.kernel_kind, r.sigma_s, r.rho, r.N,
+                           precision, base, base + abf_stack_bytes(r.h, r.w, r.N, precision), s, b);
+    if (e != hipSuccess) return ABF_E_HIP;
+    const abf_status st = range_batch(r.img, r.theta, r.sigma, r.h, r.w, r.pitch, r.N, precision,
+                                      flags, base, r.out, r.out_pitch, s, b);
     if (st != ABF_OK) return st;
-    ws += need;
   }
   return ABF_OK;
 }

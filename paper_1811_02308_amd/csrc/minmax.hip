@@ -173,9 +173,12 @@ __global__ __launch_bounds__(kThreads) void minmax_tile(
     float* __restrict__ out_a, float* __restrict__ out_b, long long op, Batch bt) {
   const FinMinMax fm;
   extern __shared__ float lds[];
-  img += blockIdx.z * bt.img;
-  out_a = byte_offset(out_a, blockIdx.z * bt.stack);
-  out_b = byte_offset(out_b, blockIdx.z * bt.stack);
+  {
+    const BatchOffsets o = bt.at(blockIdx.z, 4);
+    img = byte_offset(img, o.img);
+    out_a = byte_offset(out_a, o.stack);
+    out_b = byte_offset(out_b, o.stack);
+  }
   // LDS row strides: odd for the padded tile and kMTX + 1 for the
   // horizontal result, so that threads walking different rows hit
   // different banks. The horizontal result takes the tile's place once the
@@ -266,9 +269,10 @@ hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rh
   const long long tp = ((long long)h + 63) / 64 * 64;   // pitch of transposed rows
   float2* t = static_cast<float2*>(scratch);
   for (int z = 0; z < b.n; ++z) {    // large radii: one image at a time through the scratch
-    const float* im = img + z * b.img;
-    float* az = byte_offset(alpha, z * b.stack);
-    float* bz = byte_offset(beta, z * b.stack);
+    const BatchOffsets o = b.at_host(z, 4);
+    const float* im = byte_offset(img, o.img);
+    float* az = byte_offset(alpha, o.stack);
+    float* bz = byte_offset(beta, o.stack);
     {
       const int ROWS = rows_per_block(Rh);
       dim3 grid((w + kTX - 1) / kTX, (h + ROWS - 1) / ROWS);

@@ -407,15 +407,18 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
   __shared__ double sh[kBoxWaves][N][kStripSlots];
   // shift amplification limit as a bound on |mid - c| / half
   const double dmax = pow(cond_max, 1.0 / N) - 1.0;
-  img += blockIdx.y * bt.img;
-  if (FUSED) {
-    fz.theta += blockIdx.y * bt.img;
-    fz.sigma += blockIdx.y * bt.img;
-    fz.out = static_cast<TS*>(fz.out) + blockIdx.y * bt.out;
+  {
+    const BatchOffsets o = bt.at(blockIdx.y, sizeof(TS));
+    img = byte_offset(img, o.img);
+    if (FUSED) {
+      fz.theta = byte_offset(fz.theta, o.theta);
+      fz.sigma = byte_offset(fz.sigma, o.sigma);
+      fz.out = byte_offset(fz.out, o.out);
+    }
+    alpha = byte_offset(alpha, o.stack);
+    beta = byte_offset(beta, o.stack);
+    mom = byte_offset(mom, o.stack);
   }
-  alpha = byte_offset(alpha, blockIdx.y * bt.stack);
-  beta = byte_offset(beta, blockIdx.y * bt.stack);
-  mom = byte_offset(mom, blockIdx.y * bt.stack);
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int gw = blockIdx.x * kBoxWaves + wv;
@@ -860,15 +863,18 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
   extern __shared__ __attribute__((aligned(16))) double vsum[];
   double* const wext = vsum + N * kTY * ES;
   float2* const vmm = reinterpret_cast<float2*>(wext + tile_wext_len(R));
-  img += blockIdx.z * bt.img;
-  if (FUSED) {
-    fz.theta += blockIdx.z * bt.img;
-    fz.sigma += blockIdx.z * bt.img;
-    fz.out = static_cast<TS*>(fz.out) + blockIdx.z * bt.out;
+  {
+    const BatchOffsets o = bt.at(blockIdx.z, sizeof(TS));
+    img = byte_offset(img, o.img);
+    if (FUSED) {
+      fz.theta = byte_offset(fz.theta, o.theta);
+      fz.sigma = byte_offset(fz.sigma, o.sigma);
+      fz.out = byte_offset(fz.out, o.out);
+    }
+    alpha = byte_offset(alpha, o.stack);
+    beta = byte_offset(beta, o.stack);
+    mom = byte_offset(mom, o.stack);
   }
-  alpha = byte_offset(alpha, blockIdx.z * bt.stack);
-  beta = byte_offset(beta, blockIdx.z * bt.stack);
-  mom = byte_offset(mom, blockIdx.z * bt.stack);
   // wext: 1-D weights of taps -(kTY-1) .. 2R+kTY-1 (zero outside [0, 2R]),
   // so the phases below apply every tap without a range test; wts = the
   // taps 0 .. 2R
@@ -1308,10 +1314,13 @@ __global__ __launch_bounds__(kWaves * kWave, N <= 6 ? 2 : 1) void moments_gauss_
   // A operand for row block b + t / 4 - 1 and register t % 4
   __shared__ double fh[kKHMax][kWave];
   __shared__ double fv[12][kWave];
-  img += blockIdx.y * bt.img;
-  alpha = byte_offset(alpha, blockIdx.y * bt.stack);
-  beta = byte_offset(beta, blockIdx.y * bt.stack);
-  mom = byte_offset(mom, blockIdx.y * bt.stack);
+  {
+    const BatchOffsets o = bt.at(blockIdx.y, sizeof(TS));
+    img = byte_offset(img, o.img);
+    alpha = byte_offset(alpha, o.stack);
+    beta = byte_offset(beta, o.stack);
+    mom = byte_offset(mom, o.stack);
+  }
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int m = lane >> 4, q = lane & 15;
@@ -1564,8 +1573,10 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   }
   if (kind == 0 && !box_tile) {
     dim3 grid((waves + kBoxWaves - 1) / kBoxWaves, b.n);
-    const int vec4 = (pitch % 4 == 0) && (b.img % 4 == 0) &&
-                     (reinterpret_cast<uintptr_t>(img) % 16 == 0);
+    // 16-byte loads where every image's rows start 16-byte aligned
+    bool rows16 = pitch % 4 == 0 && b.img % 4 == 0 && reinterpret_cast<uintptr_t>(img) % 16 == 0;
+    for (int z = 0; b.host_tab && z < b.n; ++z) rows16 = rows16 && b.host_tab[z].img % 16 == 0;
+    const int vec4 = rows16 ? 1 : 0;
     if (fs)
       hipLaunchKernelGGL((moments_box<N, TS, true>), grid, dim3(kBoxWaves * kWave), 0, stream,
                          img, pitch, h, w, R, alpha, beta, sp, mom, plane, g, cond_max, vec4, b, fz);

@@ -54,13 +54,13 @@ __global__ __launch_bounds__(256) void range_kernel(
   const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (x >= W || y >= H) return;
   {
-    const long long z = blockIdx.z;
-    alpha = byte_offset(alpha, z * bt.stack);
-    beta = byte_offset(beta, z * bt.stack);
-    mom = byte_offset(mom, z * bt.stack);
-    theta += z * bt.img;
-    sigma += z * bt.img;
-    out += z * bt.out;
+    const BatchOffsets o = bt.at(blockIdx.z, sizeof(TO));
+    alpha = byte_offset(alpha, o.stack);
+    beta = byte_offset(beta, o.stack);
+    mom = byte_offset(mom, o.stack);
+    theta = byte_offset(theta, o.theta);
+    sigma = byte_offset(sigma, o.sigma);
+    out = byte_offset(out, o.out);
   }
   const long long row = (long long)y * sp;
   const unsigned bx4 = (unsigned)x * 4u;

@@ -180,6 +180,50 @@ static void batches() {
           ABF_E_WORKSPACE);
     CHECK(abf_fast_batched(reqs.data(), 0, prec, ABF_FLAG_CLAMP, nullptr, 0, nullptr) == ABF_OK);
   }
+  // requests that share launches: groups of one shape and parameter set
+  // (theta given by all or none), each request with its own buffers, mixed
+  // with single requests; radii on both sides of the bounds kernel's tile
+  // limit (the larger ones loop over the images on the host)
+  for (int rho : {3, 40}) {
+    std::vector<abf_request> g;
+    for (int i = 0; i < 7; ++i) {
+      const bool odd = i % 3 == 2;
+      const int h = odd ? 30 : 23, w = odd ? 19 : 41;
+      const long long pitch = w + 5;
+      Buf* a = new Buf(sizeof(float) * pitch * h);
+      Buf* t = new Buf(sizeof(float) * pitch * h);
+      Buf* s = new Buf(sizeof(float) * pitch * h);
+      Buf* o = new Buf(sizeof(double) * (w + 2) * h);
+      keep.insert(keep.end(), {a, t, s, o});
+      g.push_back(abf_request{a->f(), i % 2 ? t->f() : nullptr, s->f(), h, w, pitch, i % 2 ? 0 : 1,
+                              0.0, rho, 5, o->p, w + 2});
+    }
+    for (int prec = 0; prec <= 1; ++prec) {
+      const size_t wsb = abf_batched_workspace_bytes(g.data(), (int)g.size(), prec);
+      Buf ws(wsb);
+      const int before = stub_calls();
+      CHECK(abf_fast_batched(g.data(), (int)g.size(), prec, ABF_FLAG_CLAMP, ws.p, wsb, nullptr) ==
+            ABF_OK);
+      CHECK(stub_calls() > before);
+      CHECK(abf_fast_batched(g.data(), (int)g.size(), prec, ABF_FLAG_CLAMP, ws.p, wsb - 1,
+                             nullptr) == ABF_E_WORKSPACE);
+    }
+  }
+  {  // four requests of one group: the offset table, then one launch per stage for all four
+    std::vector<abf_request> g;
+    for (int i = 0; i < 4; ++i) {
+      Buf* a = new Buf(sizeof(float) * 64 * 20);
+      Buf* s = new Buf(sizeof(float) * 64 * 20);
+      Buf* o = new Buf(sizeof(float) * 64 * 20);
+      keep.insert(keep.end(), {a, s, o});
+      g.push_back(abf_request{a->f(), nullptr, s->f(), 20, 60, 64, 0, 0.0, 3, 5, o->p, 64});
+    }
+    const size_t wsb = abf_batched_workspace_bytes(g.data(), 4, 1);
+    Buf ws(wsb);
+    const int before = stub_calls();
+    CHECK(abf_fast_batched(g.data(), 4, 1, ABF_FLAG_CLAMP, ws.p, wsb, nullptr) == ABF_OK);
+    CHECK(stub_calls() - before == 4);    // table, bounds, moments, range
+  }
   abf_request bad = reqs[1];
   bad.N = ABF_N_MAX + 1;
   CHECK(abf_batched_workspace_bytes(&bad, 1, 1) == 0 ||

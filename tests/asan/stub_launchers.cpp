@@ -31,14 +31,20 @@ void need(const void* p, unsigned long long bytes, const char* what) {
   ++g_bad;
 }
 
+enum Field { kImg, kTheta, kSigma, kStack, kOut };
+
 // A plane of h rows of `pitch` elements of `elem` bytes (its last row needs
-// only w elements), for each of the batch's n images at byte stride `stride`.
-void plane(const void* p, long long pitch, int h, int w, size_t elem, int n, long long stride,
-           const char* what) {
+// only w elements), for each of the batch's images at the byte offset the
+// batch gives for `field` (its strides, or its host offset table).
+void plane(const void* p, long long pitch, int h, int w, size_t elem, const abf::Batch& b,
+           Field field, const char* what) {
   if (h < 1 || w < 1) return;
   const unsigned long long bytes = ((unsigned long long)(h - 1) * pitch + w) * elem;
-  for (int z = 0; z < n; ++z)
-    need(static_cast<const char*>(p) + (long long)z * stride, bytes, what);
+  for (int z = 0; z < b.n; ++z) {
+    const abf::BatchOffsets o = b.at_host(z, (int)elem);
+    const long long off[] = {o.img, o.theta, o.sigma, o.stack, o.out};
+    need(static_cast<const char*>(p) + off[field], bytes, what);
+  }
 }
 }  // namespace
 
@@ -56,9 +62,9 @@ hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rh
                          float* beta, long long out_pitch, void* scratch, hipStream_t,
                          const Batch& b) {
   ++g_calls;
-  plane(img, pitch, h, w, 4, b.n, b.img * 4, "minmax img");
-  plane(alpha, out_pitch, h, w, 4, b.n, b.stack, "minmax alpha");
-  plane(beta, out_pitch, h, w, 4, b.n, b.stack, "minmax beta");
+  plane(img, pitch, h, w, 4, b, kImg, "minmax img");
+  plane(alpha, out_pitch, h, w, 4, b, kStack, "minmax alpha");
+  plane(beta, out_pitch, h, w, 4, b, kStack, "minmax beta");
   if (rho > 24) need(scratch, (unsigned long long)w * ((h + 63) / 64 * 64) * 8, "minmax scratch");
   return hipSuccess;
 }
@@ -68,18 +74,17 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w, int, 
                           long long plane_elems, hipStream_t, const Batch& b, const FuseSpec* fz,
                           bool) {
   ++g_calls;
-  plane(img, pitch, h, w, 4, b.n, b.img * 4, "moments img");
-  plane(alpha, sp, h, w, 4, b.n, b.stack, "moments alpha");
-  plane(beta, sp, h, w, 4, b.n, b.stack, "moments beta");
+  plane(img, pitch, h, w, 4, b, kImg, "moments img");
+  plane(alpha, sp, h, w, 4, b, kStack, "moments alpha");
+  plane(beta, sp, h, w, 4, b, kStack, "moments beta");
   const size_t e = prec == 0 ? 8 : 4;
   if (!fz || fz->keep_stack)
     for (int k = 0; k < N; ++k)
-      plane(static_cast<const char*>(mom) + (size_t)k * plane_elems * e, sp, h, w, e, b.n,
-            b.stack, "moments plane");
+      plane(static_cast<const char*>(mom) + (size_t)k * plane_elems * e, sp, h, w, e, b, kStack, "moments plane");
   if (fz) {
-    plane(fz->theta, fz->tpitch, h, w, 4, b.n, b.img * 4, "fused theta");
-    plane(fz->sigma, fz->tpitch, h, w, 4, b.n, b.img * 4, "fused sigma");
-    plane(fz->out, fz->opitch, h, w, e, b.n, b.out * (long long)e, "fused out");
+    plane(fz->theta, fz->tpitch, h, w, 4, b, kTheta, "fused theta");
+    plane(fz->sigma, fz->tpitch, h, w, 4, b, kSigma, "fused sigma");
+    plane(fz->out, fz->opitch, h, w, e, b, kOut, "fused out");
   }
   return hipSuccess;
 }
@@ -90,11 +95,11 @@ hipError_t launch_recursive_moments(const float* img, long long pitch, int h, in
                                    hipStream_t) {
   ++g_calls;
   const size_t e = prec == 0 ? 8 : 4;
-  plane(img, pitch, h, w, 4, 1, 0, "recursive img");
-  plane(alpha, sp, h, w, 4, 1, 0, "recursive alpha");
-  plane(beta, sp, h, w, 4, 1, 0, "recursive beta");
+  plane(img, pitch, h, w, 4, abf::Batch(), kImg, "recursive img");
+  plane(alpha, sp, h, w, 4, abf::Batch(), kImg, "recursive alpha");
+  plane(beta, sp, h, w, 4, abf::Batch(), kImg, "recursive beta");
   for (int k = 0; k < N; ++k)
-    plane(static_cast<const char*>(mom) + (size_t)k * plane_elems * e, sp, h, w, e, 1, 0,
+    plane(static_cast<const char*>(mom) + (size_t)k * plane_elems * e, sp, h, w, e, abf::Batch(), kImg,
           "recursive plane");
   need(scratch, recursive_scratch_bytes(h, w, N), "recursive scratch");
   return hipSuccess;
@@ -120,14 +125,14 @@ hipError_t launch_range(const float* alpha, const float* beta, long long sp, con
                         unsigned, void* out, long long opitch, hipStream_t, const Batch& b) {
   ++g_calls;
   const size_t e = prec == 0 ? 8 : 4;
-  plane(alpha, sp, h, w, 4, b.n, b.stack, "range alpha");
-  plane(beta, sp, h, w, 4, b.n, b.stack, "range beta");
+  plane(alpha, sp, h, w, 4, b, kStack, "range alpha");
+  plane(beta, sp, h, w, 4, b, kStack, "range beta");
   for (int k = 0; k < N; ++k)
-    plane(static_cast<const char*>(mom) + (size_t)k * plane_elems * e, sp, h, w, e, b.n, b.stack,
+    plane(static_cast<const char*>(mom) + (size_t)k * plane_elems * e, sp, h, w, e, b, kStack,
           "range plane");
-  plane(theta_or_img, tpitch, h, w, 4, b.n, b.img * 4, "range theta");
-  plane(sigma, spitch, h, w, 4, b.n, b.img * 4, "range sigma");
-  plane(out, opitch, h, w, e, b.n, b.out * (long long)e, "range out");
+  plane(theta_or_img, tpitch, h, w, 4, b, kTheta, "range theta");
+  plane(sigma, spitch, h, w, 4, b, kSigma, "range sigma");
+  plane(out, opitch, h, w, e, b, kOut, "range out");
   return hipSuccess;
 }
 
@@ -138,21 +143,21 @@ hipError_t launch_range_uniform(const float* alpha, const float* beta, long long
                                 long long opitch, hipStream_t) {
   ++g_calls;
   const size_t e = prec == 0 ? 8 : 4;
-  plane(alpha, sp, h, w, 4, 1, 0, "uniform alpha");
-  plane(beta, sp, h, w, 4, 1, 0, "uniform beta");
-  plane(mom1, sp, h, w, e, 1, 0, "uniform plane 1");
-  plane(img, ipitch, h, w, 4, 1, 0, "uniform img");
-  plane(theta_or_img, tpitch, h, w, 4, 1, 0, "uniform theta");
-  plane(sigma, spitch, h, w, 4, 1, 0, "uniform sigma");
-  plane(out, opitch, h, w, e, 1, 0, "uniform out");
+  plane(alpha, sp, h, w, 4, abf::Batch(), kImg, "uniform alpha");
+  plane(beta, sp, h, w, 4, abf::Batch(), kImg, "uniform beta");
+  plane(mom1, sp, h, w, e, abf::Batch(), kImg, "uniform plane 1");
+  plane(img, ipitch, h, w, 4, abf::Batch(), kImg, "uniform img");
+  plane(theta_or_img, tpitch, h, w, 4, abf::Batch(), kImg, "uniform theta");
+  plane(sigma, spitch, h, w, 4, abf::Batch(), kImg, "uniform sigma");
+  plane(out, opitch, h, w, e, abf::Batch(), kImg, "uniform out");
   return hipSuccess;
 }
 
 hipError_t launch_sigma_std(const float* img, long long pitch, int h, int w, int, double, double,
                             double, float* out, long long opitch, hipStream_t, const Batch& b) {
   ++g_calls;
-  plane(img, pitch, h, w, 4, b.n, b.img * 4, "sigma img");
-  plane(out, opitch, h, w, 4, b.n, b.out * 4, "sigma out");
+  plane(img, pitch, h, w, 4, b, kImg, "sigma img");
+  plane(out, opitch, h, w, 4, b, kOut, "sigma out");
   return hipSuccess;
 }
 
@@ -162,9 +167,9 @@ hipError_t launch_sharpen_maps(const float* img, long long pitch, int h, int w, 
                                double, double, double, float* theta, float* sigma, long long op,
                                hipStream_t, const Batch& b) {
   ++g_calls;
-  plane(img, pitch, h, w, 4, b.n, b.img * 4, "sharpen img");
-  plane(theta, op, h, w, 4, b.n, b.out * 4, "sharpen theta");
-  plane(sigma, op, h, w, 4, b.n, b.out * 4, "sharpen sigma");
+  plane(img, pitch, h, w, 4, b, kImg, "sharpen img");
+  plane(theta, op, h, w, 4, b, kOut, "sharpen theta");
+  plane(sigma, op, h, w, 4, b, kOut, "sharpen sigma");
   return hipSuccess;
 }
 
@@ -172,8 +177,8 @@ hipError_t launch_mrtv_sigma(const float* img, long long pitch, int h, int w, in
                              double, double, float* sigma, long long op, hipStream_t,
                              const Batch& b) {
   ++g_calls;
-  plane(img, pitch, h, w, 4, b.n, b.img * 4, "mrtv img");
-  plane(sigma, op, h, w, 4, b.n, b.out * 4, "mrtv sigma");
+  plane(img, pitch, h, w, 4, b, kImg, "mrtv img");
+  plane(sigma, op, h, w, 4, b, kOut, "mrtv sigma");
   return hipSuccess;
 }
 
@@ -181,8 +186,8 @@ hipError_t launch_grey(const float* rgb, long long pitch, long long cstride, int
                        float* out, long long op, hipStream_t, const Batch& b) {
   ++g_calls;
   for (int c = 0; c < 3; ++c)
-    plane(rgb + c * cstride, pitch, h, w, 4, b.n, b.img * 4, "grey rgb");
-  plane(out, op, h, w, 4, b.n, b.out * 4, "grey out");
+    plane(rgb + c * cstride, pitch, h, w, 4, b, kImg, "grey rgb");
+  plane(out, op, h, w, 4, b, kOut, "grey out");
   return hipSuccess;
 }
 
@@ -190,10 +195,24 @@ hipError_t launch_brute(const float* img, const float* theta, const float* sigma
                         int h, int w, int, double, int, int prec, void* out, long long opitch,
                         hipStream_t) {
   ++g_calls;
-  plane(img, pitch, h, w, 4, 1, 0, "brute img");
-  plane(theta, pitch, h, w, 4, 1, 0, "brute theta");
-  plane(sigma, pitch, h, w, 4, 1, 0, "brute sigma");
-  plane(out, opitch, h, w, prec == 0 ? 8 : 4, 1, 0, "brute out");
+  plane(img, pitch, h, w, 4, abf::Batch(), kImg, "brute img");
+  plane(theta, pitch, h, w, 4, abf::Batch(), kImg, "brute theta");
+  plane(sigma, pitch, h, w, 4, abf::Batch(), kImg, "brute sigma");
+  plane(out, opitch, h, w, prec == 0 ? 8 : 4, abf::Batch(), kImg, "brute out");
+  return hipSuccess;
+}
+
+hipError_t launch_write_offsets(BatchOffsets* dev, const BatchOffsets* host, int n,
+                                hipStream_t) {
+  ++g_calls;
+  need(dev, (unsigned long long)n * sizeof(BatchOffsets), "offset table");
+  for (int i = 0; i < n; ++i) {    // every member's planes must be reachable from its group's first
+    const BatchOffsets& o = host[i];
+    if ((o.img | o.theta | o.sigma | o.out) % 4 != 0 || o.stack % 256 != 0) {
+      std::fprintf(stderr, "stub: offset record %d is misaligned\n", i);
+      ++g_bad;
+    }
+  }
   return hipSuccess;
 }
 

@@ -282,6 +282,50 @@ def test_batched_equals_single_and_deterministic(torch, abf):
         assert torch.equal(a, b) and torch.equal(a, c)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batched_groups_equal_single(torch, abf, precision):
+    """Requests that share launches (one shape and parameter set, each with
+    its own buffers, some as row-pitched views) give exactly abf_fast's
+    output: box kernel (strip kernel), Gaussian (tile kernel taking the
+    bounds), a radius above the bounds kernel's tile limit (its per-image
+    host loop), theta given or not, mixed with single requests and the
+    recursive kernel (one image per launch)."""
+    specs = [(60, 90, "box", 4, 5, False), (60, 90, "box", 4, 5, False), (41, 130, "gaussian", 6, 6, True),
+             (60, 90, "box", 4, 5, False), (41, 130, "gaussian", 6, 6, True), (70, 50, "box", 30, 7, False),
+             (70, 50, "box", 30, 7, False), (33, 47, "box", 2, 3, False), (41, 130, "gaussian", 6, 6, True)]
+    if precision == "mixed":
+        specs += [(50, 60, "recursive", 5, 6, False), (50, 60, "recursive", 5, 6, False)]
+    items, singles = [], []
+    for i, (h, w, kernel, R, N, with_theta) in enumerate(specs):
+        f = rect_scene(300 + i, h, w, n_rect=4, noise=8, side_lo=4, side_hi=30)
+        sg = smooth_field(np.random.default_rng(i), h, w, 8, 35)
+        img = dev(torch, f)
+        if i % 3 == 1:       # a row-pitched view into a wider buffer
+            wide = torch.zeros((h, w + 13), dtype=torch.float32, device="cuda")
+            wide[:, 3:3 + w] = img
+            img = wide[:, 3:3 + w]
+            sgw = torch.zeros((h, w + 13), dtype=torch.float32, device="cuda")
+            sgw[:, 3:3 + w] = dev(torch, sg)
+            sgd = sgw[:, 3:3 + w]
+        else:
+            sgd = dev(torch, sg)
+        th = None
+        if with_theta:
+            th = img + dev(torch, smooth_field(np.random.default_rng(50 + i), h, w, -15, 15))
+            if i % 3 == 1:
+                thw = torch.zeros((h, w + 13), dtype=torch.float32, device="cuda")
+                thw[:, 3:3 + w] = th
+                th = thw[:, 3:3 + w]
+        it = dict(img=img, sigma=sgd, theta=th, kernel=kernel, rho=R, N=N)
+        items.append(it)
+        singles.append(abf.fast(img, sgd, theta=th, kernel=kernel, rho=R, N=N, precision=precision))
+    outs = abf.fast_batched(items, precision=precision)
+    outs2 = abf.fast_batched(items, precision=precision)
+    torch.cuda.synchronize()
+    for i, (a, b, c) in enumerate(zip(outs, singles, outs2)):
+        assert torch.equal(a, b) and torch.equal(a, c), i
+
+
 def test_stack_reuse_for_new_theta_sigma(torch, abf):
     f = rect_scene(41, 90, 120, n_rect=5, noise=10, side_lo=6, side_hi=40)
     st = abf.moment_stack(dev(torch, f), rho=4, N=6, precision="mixed")
