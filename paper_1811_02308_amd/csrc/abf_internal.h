@@ -122,6 +122,44 @@ __device__ __forceinline__ T at_byte(const T* p, unsigned byte_off) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
 }
 
+// Raw buffer access for a wave-uniform base address: the resource holds the
+// base in scalar registers (stride 0, the largest record count, so nothing
+// within 4 GiB of the base is clipped) and each lane supplies a 32-bit byte
+// offset, so no lane does 64-bit address arithmetic. Loads and stores go
+// through the vector memory path (buffer_load / buffer_store).
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld_f32(BufRsrc r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld_f64(BufRsrc r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ float4 buf_ld_f32x4(BufRsrc r, unsigned off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(BufRsrc r, unsigned off, const float*) {
+  return buf_ld_f32(r, off);
+}
+__device__ __forceinline__ double buf_ld(BufRsrc r, unsigned off, const double*) {
+  return buf_ld_f64(r, off);
+}
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)off, 0, 0);
+}
+typedef unsigned int BufU32x2 __attribute__((__vector_size__(8)));
+__device__ __forceinline__ void buf_st(BufRsrc r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU32x2, v), r, (int)off, 0, 0);
+}
+
+// p[i] = v for a wave-uniform base p and a per-lane 32-bit byte offset.
+template <typename T>
+__device__ __forceinline__ void st_byte(T* p, unsigned byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + byte_off) = v;
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ T* byte_offset(T* p, long long bytes) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<void*>(static_cast<const void*>(p))) + bytes);

@@ -61,7 +61,19 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // v + (value of v `ctrl` DPP positions away), 0 where the source lane is
-// outside the pattern (rows masked by row_mask keep 0).
+// outside its row (row shifts: the lane reads 0 by the bound control, so no
+// register has to be cleared first).
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr_add(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xf, 0xf, true);
+  const long long tb = ((long long)hi << 32) | (long long)(unsigned)lo;
+  return v + __longlong_as_double(tb);
+}
+
+// The same for the row broadcasts, where the rows that row_mask leaves out
+// keep the cleared value 0.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_add(double v) {
   const long long bits = __double_as_longlong(v);
@@ -76,10 +88,10 @@ __device__ __forceinline__ double dpp_add(double v) {
 // carry row totals into the rows above.
 __device__ __forceinline__ double wave_inclusive_scan(double v, int lane) {
   (void)lane;
-  v = dpp_add<0x111, 0xf>(v);   // row_shr:1
-  v = dpp_add<0x112, 0xf>(v);   // row_shr:2
-  v = dpp_add<0x114, 0xf>(v);   // row_shr:4
-  v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+  v = dpp_shr_add<0x111>(v);    // row_shr:1
+  v = dpp_shr_add<0x112>(v);    // row_shr:2
+  v = dpp_shr_add<0x114>(v);    // row_shr:4
+  v = dpp_shr_add<0x118>(v);    // row_shr:8
   v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 -> rows 1, 3
   v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 -> rows 2, 3
   return v;
@@ -168,10 +180,10 @@ __device__ __forceinline__ void finish_pixel(const double (&m)[N + 1], float a, 
     if (a == b) {
       *o = TS(a);
     } else {
-      double ak[N + 1];
+      double ak[N + 1];                  // a~_k as stored in the stack
       ak[0] = 1.0;
 #pragma unroll
-      for (int k = 1; k <= N; ++k) ak[k] = (2.0 * k + 1.0) * (double)TS(m[k]);
+      for (int k = 1; k <= N; ++k) ak[k] = (double)TS(m[k]);
       const long long ti = (long long)y * fz.tpitch + x;
       *o = TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)fz.theta[ti], (double)fz.sigma[ti],
                                               fz.flags, fz.gl));
@@ -289,13 +301,13 @@ __device__ __forceinline__ void load_bounds_row(const float* __restrict__ alpha,
                                                 const float* __restrict__ beta, long long sp,
                                                 int y, int xo, int O, int W, int lane,
                                                 float (&pa)[kChunks], float (&pb)[kChunks]) {
-  const float* ar = alpha + (long long)y * sp;
-  const float* br = beta + (long long)y * sp;
+  const BufRsrc ar = buf_rsrc(alpha + (long long)y * sp);
+  const BufRsrc br = buf_rsrc(beta + (long long)y * sp);
 #pragma unroll
   for (int q = 0; q < kChunks; ++q) {
-    const unsigned x = (unsigned)min(xo + min(q * kWave + lane, O - 1), W - 1);
-    pa[q] = ar[x];
-    pb[q] = br[x];
+    const unsigned x4 = (unsigned)min(xo + min(q * kWave + lane, O - 1), W - 1) * 4u;
+    pa[q] = buf_ld_f32(ar, x4);
+    pb[q] = buf_ld_f32(br, x4);
   }
 }
 
@@ -420,7 +432,9 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
     mom = byte_offset(mom, o.stack);
   }
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  // (wave-uniform, so that the strip geometry and every row base below are
+  // scalar values)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int gw = blockIdx.x * kBoxWaves + wv;
   if (gw >= g.n_strips * g.n_segs) return;
   const FinMinMax fm;
@@ -440,13 +454,16 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
   // the lane's 4 columns as one aligned float4 when they are all inside the
   // image (xs is a multiple of 4) and rows are 16-byte aligned
   const bool v4 = vec4 && xs + kV * lane >= 0 && xs + kV * lane + kV <= W;
+  // (rows are wave-uniform: each load takes the row from a buffer resource
+  // in scalar registers and the lane's column as a 32-bit byte offset)
   auto load4 = [&](const float* row, float (&q)[kV]) {
+    const BufRsrc r = buf_rsrc(row);
     if (v4) {
-      const float4 t4 = *reinterpret_cast<const float4*>(row + xs + kV * lane);
+      const float4 t4 = buf_ld_f32x4(r, (unsigned)(xs + kV * lane) * 4u);
       q[0] = t4.x; q[1] = t4.y; q[2] = t4.z; q[3] = t4.w;
     } else {
 #pragma unroll
-      for (int v = 0; v < kV; ++v) q[v] = row[cx[v]];
+      for (int v = 0; v < kV; ++v) q[v] = buf_ld_f32(r, (unsigned)cx[v] * 4u);
     }
   };
 
@@ -521,6 +538,7 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
       d[pidx(kV * lane + 3)] = incl;
     }
     wave_sync();
+    TS* const mrow = mom + (long long)y * sp;
     // epilogue: lanes take consecutive output columns, chunk q = columns
     // 64 q .. 64 q + 63 of the strip's outputs. The chunks have no branch
     // between them (a flat window's zero moments are selected, and the
@@ -544,8 +562,17 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
 #pragma unroll
         for (int k = 1; k <= N; ++k) m[k] = 0.0;
       }
-      if (valid && !bad) finish_pixel<N, TS, FUSED>(m, a, b, y, x, (long long)y * sp + x, mom,
-                                                    plane, fz);
+      if (valid && !bad) {
+        if (FUSED) {
+          finish_pixel<N, TS, FUSED>(m, a, b, y, x, (long long)y * sp + x, mom, plane, fz);
+        } else {
+          // the row's plane bases are wave-uniform: buffer resources in
+          // scalar registers, one 32-bit byte offset per lane
+          const unsigned xb = (unsigned)x * (unsigned)sizeof(TS);
+#pragma unroll
+          for (int k = 1; k <= N; ++k) buf_st(buf_rsrc(mrow + (k - 1) * plane), xb, TS(m[k]));
+        }
+      }
       if (valid && bad) badq |= 1u << q;
     };
     if (FUSED) {

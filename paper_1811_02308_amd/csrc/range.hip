@@ -62,22 +62,25 @@ __global__ __launch_bounds__(256) void range_kernel(
     sigma = byte_offset(sigma, o.sigma);
     out = byte_offset(out, o.out);
   }
+  // every row base is wave-uniform: buffer resources in scalar registers,
+  // one 32-bit byte offset per lane
   const long long row = (long long)y * sp;
   const unsigned bx4 = (unsigned)x * 4u;
-  const float a = at_byte(alpha + row, bx4), b = at_byte(beta + row, bx4);
-  TO* o = out + (long long)y * opitch + x;
+  const float a = buf_ld_f32(buf_rsrc(alpha + row), bx4), b = buf_ld_f32(buf_rsrc(beta + row), bx4);
+  const BufRsrc orow = buf_rsrc(out + (long long)y * opitch);
+  const unsigned bxo = (unsigned)x * (unsigned)sizeof(TO);
   if (a == b) {
-    *o = TO(a);
+    buf_st(orow, bxo, TO(a));
     return;
   }
-  double ak[N + 1];                      // (2k+1) a~_k
-  ak[0] = 1.0;
+  double at[N + 1];                      // a~_k
+  at[0] = 1.0;
   const unsigned bxs = (unsigned)x * (unsigned)sizeof(TS);
 #pragma unroll
-  for (int k = 1; k <= N; ++k)
-    ak[k] = (2.0 * k + 1.0) * (double)at_byte(mom + (k - 1) * plane + row, bxs);
-  *o = TO(range_eval<N, kMixed>(a, b, ak, (double)at_byte(theta + (long long)y * tpitch, bx4),
-                                (double)at_byte(sigma + (long long)y * spitch, bx4), flags, gl));
+  for (int k = 1; k <= N; ++k) at[k] = buf_ld(buf_rsrc(mom + (k - 1) * plane + row), bxs, mom);
+  const double th = buf_ld_f32(buf_rsrc(theta + (long long)y * tpitch), bx4);
+  const double sg = buf_ld_f32(buf_rsrc(sigma + (long long)y * spitch), bx4);
+  buf_st(orow, bxo, TO(range_eval<N, kMixed>(a, b, at, th, sg, flags, gl)));
 }
 
 

@@ -27,6 +27,25 @@ inline GLArgs make_gl_args(bool mixed) {
 
 constexpr double kSqrtPi = 1.7724538509055160273;
 
+// The fit c = A^-1 mu of eq. inv in the Legendre form: p(t) = sum_k (2k+1)
+// a~_k P_k(2t - 1). fit.ell[k][r] = (2k+1) ell[k][r] gives p's coefficients
+// in powers of t from the Legendre moments a~_k, fit.leg[k][r] = (2k+1)
+// L[k][r] in powers of x = 2t - 1 (products of small integers and dyadic
+// rationals: exact, so folding the factor in changes no result bit).
+struct FitTables {
+  double ell[kNMax + 1][kNMax + 1];
+  double leg[kNMax + 1][kNMax + 1];
+  constexpr FitTables() : ell{}, leg{} {
+    const ShiftedLegTable SL;
+    const LegTable LT;
+    for (int k = 0; k <= kNMax; ++k)
+      for (int r = 0; r <= kNMax; ++r) {
+        ell[k][r] = (2.0 * k + 1.0) * SL.ell[k][r];
+        leg[k][r] = (2.0 * k + 1.0) * LT.L[k][r];
+      }
+  }
+};
+
 // Smallest lambda at which the forward recursion is used, per degree N.
 // The recursion's rounding grows roughly like N!/(2 lambda)^N; these limits
 // keep its error in F below ~1e-10 (FP64 path) and ~1e-6 (mixed path),
@@ -94,15 +113,14 @@ __device__ __forceinline__ double erfcx_w(double x) {
 }
 
 // g^ = a + (b - a) F for one pixel and the interval [a, b] (a < b; the
-// window bounds alpha, beta in Algorithm 1). ak[k] = (2k+1) a~_k with
-// ak[0] = 1; th = theta, sg = sigma at the pixel.
+// window bounds alpha, beta in Algorithm 1). at[k] = a~_k, the Legendre
+// moments, with at[0] = 1; th = theta, sg = sigma at the pixel.
 // kMixed selects the mixed-precision thresholds, node count and FP32
 // quadrature exponentials.
 template <int N, bool kMixed>
-__device__ __forceinline__ double range_eval(double a, double b, const double (&ak)[N + 1], double th,
+__device__ __forceinline__ double range_eval(double a, double b, const double (&at)[N + 1], double th,
                                              double sg, unsigned flags, const GLArgs& gl) {
-  constexpr ShiftedLegTable SL{};
-  constexpr LegTable LT{};
+  constexpr FitTables FT{};
   constexpr int Q = kMixed ? kGLNodesMixed : kGLNodes;
   const double da = a, delta = b - da;
   double t0, lam, sl;
@@ -134,7 +152,7 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
     for (int r = 0; r <= N; ++r) {
       double acc = 0.0;
 #pragma unroll
-      for (int k = r; k <= N; ++k) acc = fma(ak[k], SL.ell[k][r], acc);
+      for (int k = r; k <= N; ++k) acc = fma(at[k], FT.ell[k][r], acc);
       c[r] = acc;
     }
     const double A = -sl * t0, B = sl * (1.0 - t0);
@@ -173,19 +191,23 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
     }
   } else {
     // support of the scaled Gaussian exp(-lam ((t-t0)^2 - dist^2)) above e^-kSupport
-    const double L = lam > 0.0 ? (kMixed ? (double)sqrtf((float)(dist * dist + kSupport / lam))
-                                         : sqrt(dist * dist + kSupport / lam)) - dist
-                               : 2.0;
+    // (a bound, not an exact quantity: reciprocal estimate and, on the
+    // mixed path, the hardware square root)
+    const double L = lam > 0.0
+                         ? (kMixed ? (double)__builtin_amdgcn_sqrtf((float)fma(kSupport, rcp(lam), dist * dist))
+                                   : sqrt(fma(kSupport, rcp(lam), dist * dist))) - dist
+                         : 2.0;
     const double lo = fmax(0.0, ts - L), hi = fmin(1.0, ts + L);
     const double span = hi - lo;
-    // p in powers of x = 2t - 1: bx[r] = sum_k ak[k] L[k][r] (coefficients of
-    // moderate size, so Horner in x on [-1, 1] is well conditioned)
+    // p in powers of x = 2t - 1: bx[r] = sum_k (2k+1) a~_k L[k][r]
+    // (coefficients of moderate size, so Horner in x on [-1, 1] is well
+    // conditioned)
     double bx[N + 1];
 #pragma unroll
     for (int r = 0; r <= N; ++r) {
       double acc = 0.0;
 #pragma unroll
-      for (int k = r; k <= N; k += 2) acc = fma(ak[k], LT.L[k][r], acc);
+      for (int k = r; k <= N; k += 2) acc = fma(at[k], FT.leg[k][r], acc);
       bx[r] = acc;
     }
     T1 = T2 = 0.0;
