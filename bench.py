@@ -1,23 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the fast adaptive bilateral filter on one MI355X.
 
-A step is one pass of the whole fast filter (window bounds, moment stack,
-range stage) over one synthetic image already resident in HBM, issued as
-the C-ABI calls abf_moment_stack -> abf_range on one stream (exactly what
-abf_fast does). The K timed steps alternate between two streams, each with
-its own stack and output buffers, so two images are in flight (one image's
-kernels fill the other's kernel tails and launch gaps), with no events
-between the kernels. The same K steps then run on one stream (the
-single-stream rate, reported beside the value) and once more on one stream
-with HIP events around every kernel, which gives each kernel's live
-duration (roofline) and the per-step device latency (p50/p99).
-Where the stack takes two kernels (abf_stack_single_pass() == 0: box and
-matrix-core moment kernels) they are issued as abf_minmax ->
-abf_stack_moments, the same two launches, so each is timed on its own; for
-the Gaussian tile kernel the stack is one launch that also takes the window
-bounds. The mixed-precision path is the headline value; the
-all-FP64 path, the fused variant (abf_minmax -> abf_moments_range, moments
-and range stage in one kernel, no moment planes in HBM) and the GPU brute
+A step is one pass of the whole fast filter over one synthetic image
+already resident in HBM, issued as exactly the launches abf_fast makes:
+window bounds (abf_minmax), then either the moment and range stages fused
+in one kernel (abf_moments_range; abf_fast_fused() says where abf_fast
+takes this path: the box kernel on the mixed path at small radii) or the
+stack path, moment stack then range stage (abf_stack_moments or, where the
+Gaussian tile kernel takes the bounds itself, abf_moment_stack in one
+launch; then abf_range). Each stage is its own C-ABI call so that each
+kernel can be timed on its own. The K timed steps alternate between two
+streams, each with its own stack and output buffers, so two images are in
+flight (one image's kernels fill the other's kernel tails and launch
+gaps), with no events between the kernels. The same K steps then run on
+one stream (the single-stream rate, reported beside the value) and once
+more on one stream with HIP events around every kernel, which gives each
+kernel's live duration (roofline) and the per-step device latency
+(p50/p99). The mixed-precision path is the headline value; the all-FP64
+path, the other path of each precision (stack where abf_fast fuses, fused
+where it does not; the outputs are identical bit for bit) and the GPU brute
 force are timed beside it. Before any step is counted, every path runs a
 fixed PREWARM_STEPS untimed steps on top of --warmup (a kernel runs slower
 in the first few hundred launches of a process).
@@ -110,6 +111,7 @@ STAGE_SOURCES = {
     "minmax": ("minmax.hip", "abf_internal.h"),
     "moments": ("moments.hip", "range_eval.h", "abf_internal.h"),
     "stack": ("moments.hip", "range_eval.h", "abf_internal.h"),
+    "moments_range": ("moments.hip", "range_eval.h", "abf_internal.h"),
     "range": ("range.hip", "range_eval.h", "abf_internal.h"),
 }
 
@@ -311,6 +313,9 @@ def main():
     fd, td, sd = dev(f), dev(th), dev(sg)
 
     single = abf.stack_single_pass(H, W, kernel, R, N)
+    # the path abf_fast takes for each precision: bounds, then the moment and
+    # range stages fused in one kernel, or the stack path
+    fuses = {p: abf.fast_fused(H, W, kernel, R, N, p) for p in ("mixed", "fp64")}
     # the timed steps alternate between two streams, each with its own stack,
     # scratch and output buffers (two images in flight: one image's kernels
     # fill the other's kernel tails and launch gaps)
@@ -395,15 +400,15 @@ def main():
         return outs[0], stage_ms, total_ms, wall, wall1
 
     # ---------------------------------------------------------- timed region
-    log("timing mixed path ...")
-    out_m, st_m, tot_m, wall_m, wall1_m = time_path("mixed", args.steps, args.warmup)
-    log("timing fp64 path ...")
-    out_d, st_d, tot_d, wall_d, wall1_d = time_path("fp64", args.steps, args.warmup)
-    log("timing the fused variant ...")
+    log(f"timing mixed path ({'fused' if fuses['mixed'] else 'stack'}) ...")
+    out_m, st_m, tot_m, wall_m, wall1_m = time_path("mixed", args.steps, args.warmup, fuses["mixed"])
+    log(f"timing fp64 path ({'fused' if fuses['fp64'] else 'stack'}) ...")
+    out_d, st_d, tot_d, wall_d, wall1_d = time_path("fp64", args.steps, args.warmup, fuses["fp64"])
+    log("timing the other path of each precision ...")
     fu_steps = max(5, args.steps // 5)
-    out_s, st_s, tot_s, wall_s, _ = time_path("mixed", fu_steps, 2, fused=True)
-    out_sd, st_sd, tot_sd, wall_sd, _ = time_path("fp64", fu_steps, 2, fused=True)
-    fused_equal = bool(torch.equal(out_s, out_m) and torch.equal(out_sd, out_d))
+    out_s, st_s, tot_s, wall_s, _ = time_path("mixed", fu_steps, 2, not fuses["mixed"])
+    out_sd, st_sd, tot_sd, wall_sd, _ = time_path("fp64", fu_steps, 2, not fuses["fp64"])
+    other_equal = bool(torch.equal(out_s, out_m) and torch.equal(out_sd, out_d))
 
     med = lambda v: float(np.median(v))
     # whole-job rate: K steps over the synchronised wall clock of the timed region
@@ -453,13 +458,15 @@ def main():
         err_d = float(np.max(np.abs(out_d.cpu().numpy()[ys, xs] - par_ref)))
         n_par = int(len(ys))
     # whole path at the roofline: the algorithmic bytes of one step (read f,
-    # theta-or-f and sigma, write the output, write and read the moment
-    # stack once) over the step's wall time
-    path_bytes = H * W * (16 + 8 * (N + 2))
+    # theta-or-f and sigma, write the output, write and read once each plane
+    # the path keeps in HBM: the whole stack, or on the fused path the window
+    # bounds only) over the step's wall time
+    planes = 2 if fuses["mixed"] else N + 2
+    path_bytes = H * W * (16 + 8 * planes)
     path_gbs = path_bytes / (ms_m * 1e-3) / 1e9
     whole = {"bound": "hbm", "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(path_gbs / HBM_PEAK_GBS, 4), "bytes_per_step": path_bytes,
-             "bytes_per_pixel": 16 + 8 * (N + 2)}
+             "bytes_per_pixel": 16 + 8 * planes}
 
     lat_m = np.array(tot_m)
     res = {
@@ -490,10 +497,13 @@ def main():
         "parity_pixels": n_par,
         "brute_force_fp64": {"value": round(mpix / (brute_ms * 1e-3), 3), "ms": round(brute_ms, 3)},
         "device_ms_per_step_median": {"mixed": round(med(tot_m), 5), "fp64": round(med(tot_d), 5)},
-        "fused_variant": {"mixed_ms_per_step": round(wall_s, 5), "fp64_ms_per_step": round(wall_sd, 5),
-                          "stage_ms_mixed": {k: round(med(v), 5) for k, v in st_s.items()},
-                          "stage_ms_fp64": {k: round(med(v), 5) for k, v in st_sd.items()},
-                          "output_equals_stack_path": fused_equal},
+        "path": {p: "fused" if f else "stack" for p, f in fuses.items()},
+        "other_path": {"path": {p: "stack" if f else "fused" for p, f in fuses.items()},
+                       "mixed_ms_per_step": round(wall_s, 5), "fp64_ms_per_step": round(wall_sd, 5),
+                       "mixed_value": round(mpix / (wall_s * 1e-3), 2),
+                       "stage_ms_mixed": {k: round(med(v), 5) for k, v in st_s.items()},
+                       "stage_ms_fp64": {k: round(med(v), 5) for k, v in st_sd.items()},
+                       "output_equals_path": other_equal},
         "roofline": roof,
         "whole_path_roofline": whole,
         "prewarm_steps": PREWARM_STEPS,

@@ -172,6 +172,15 @@ enum { ABF_STACK_BOUNDS_ONLY = 0, ABF_STACK_BOX = 1, ABF_STACK_TILE = 2,
 int abf_stack_kernel(int h, int w, int kernel_kind, int rho, int N, int precision);
 
 /*
+ * abf_fast_fused -- 1 if abf_fast (and abf_fast_strided, and the shared
+ * launches of abf_fast_batched) run the moment and range stages of
+ * Algorithm 1 fused in one kernel for these arguments: the box kernel on
+ * the mixed path at rho <= 8, where the fused kernel was measured faster on
+ * MI355X. 0 for the stack path and for invalid arguments. Host only.
+ */
+int abf_fast_fused(int h, int w, int kernel_kind, int rho, int N, int precision);
+
+/*
  * abf_stack_moments -- the second half of abf_moment_stack: given a stack
  * whose planes 0 and 1 already hold alpha_i and beta_i for this image and
  * rho (e.g. written by abf_minmax with out_pitch = abf_stack_pitch(w)),
@@ -224,9 +233,13 @@ abf_status abf_moments_range(const float* img, const float* theta, const float* 
 
 /*
  * abf_fast -- the whole fast filter (Algorithm 1) on one image:
- * abf_moment_stack into the front of `workspace`, then abf_range.
+ * abf_moment_stack into the front of `workspace`, then abf_range; or, where
+ * abf_fast_fused() is 1, abf_minmax into the stack's bounds planes and then
+ * abf_moments_range (moments and range stage in one kernel, the moment
+ * planes never written). Both give the same output bit for bit.
  * workspace >= abf_workspace_bytes(h, w, rho, N, precision), 256-byte
- * aligned. theta, sigma share `pitch` with img.
+ * aligned. theta, sigma share `pitch` with img. Only ABF_FLAG_CLAMP of
+ * `flags` is used.
  */
 abf_status abf_fast(const float* img, const float* theta, const float* sigma,
                     int h, int w, long long pitch, int kernel_kind, double sigma_s,

@@ -79,6 +79,7 @@ def lib():
         "abf_stack_single_pass": ([i, i, i, i, i], i),
         "abf_fast_noalloc": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, ll, vp], i),
         "abf_stack_kernel": ([i, i, i, i, i, i], i),
+        "abf_fast_fused": ([i, i, i, i, i, i], i),
         "abf_stack_moments": ([vp, i, i, ll, i, d, i, i, i, vp, sz, vp], i),
         "abf_range": ([vp, sz, vp, vp, vp, i, i, ll, i, i, u, vp, ll, vp], i),
         "abf_moments_range": ([vp, vp, vp, i, i, ll, i, d, i, i, i, u, vp, sz, vp, ll, vp], i),
@@ -281,6 +282,12 @@ def stack_kernel(h, w, kernel="box", rho=3, N=5, precision="mixed"):
     if k < 0:
         raise ABFError("abf_stack_kernel: invalid arguments")
     return STACK_KERNELS[k]
+
+
+def fast_fused(h, w, kernel="box", rho=3, N=5, precision="mixed"):
+    """abf_fast_fused: whether abf_fast runs the moment and range stages fused
+    in one kernel for these arguments (else the stack path)."""
+    return bool(lib().abf_fast_fused(int(h), int(w), _kind(kernel), int(rho), int(N), _prec(precision)))
 
 
 def minmax_into_stack(img, stack, rho, N, precision="mixed", workspace=None, stream=None):

@@ -201,6 +201,12 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w,
 
 bool moments_fusable(int kernel_kind, int rho, int N, long long h, long long w);
 
+// Whether abf_fast runs the moment and range stages fused (launch_moments
+// with a FuseSpec after launch_minmax) rather than the stack path; prec 1 =
+// mixed. The box kernel's segment geometry follows the same choice.
+constexpr int kFuseRhoMax = 8;
+bool fast_fuses(int kernel_kind, int rho, int N, int prec);
+
 // Moment planes for the recursive approximation of the Gaussian (kernel kind
 // 2): the alpha/beta planes must hold the window bounds; `scratch` (device,
 // 256-byte aligned) >= recursive_scratch_bytes(h, w, N).

@@ -306,6 +306,40 @@ abf_status abf_moments_range(const float* img, const float* theta, const float* 
                              static_cast<hipStream_t>(stream), abf::Batch(), true);
 }
 
+// Algorithm 1 on one image or a batch (arguments checked by the caller):
+// the window bounds, then the moment and range stages fused where
+// abf::fast_fuses() holds, else the stack path (moment stack, then range
+// stage). `stack` holds the image's (or batch's) stacks, `scratch` the
+// bounds scratch.
+static abf_status fast_stages(const float* img, const float* theta, const float* sigma, int h,
+                              int w, long long pitch, int kernel_kind, double sigma_s, int rho,
+                              int N, int precision, unsigned flags, char* stack, void* scratch,
+                              void* out, long long out_pitch, hipStream_t s,
+                              const abf::Batch& b) {
+  const unsigned rflags = flags & ABF_FLAG_CLAMP;
+  if (N > 0 && abf::fast_fuses(kernel_kind, rho, N, precision == ABF_PREC_MIXED ? 1 : 0)) {
+    const long long sp = abf_stack_pitch(w);
+    float* alpha = reinterpret_cast<float*>(stack);
+    float* beta = reinterpret_cast<float*>(stack + abf_stack_plane_offset(h, w, N, precision, 1));
+    if (abf::launch_minmax(img, pitch, h, w, rho, alpha, beta, sp, scratch, s, b) != hipSuccess)
+      return ABF_E_HIP;
+    return moments_range_batch(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N,
+                               precision, rflags, stack, out, out_pitch, s, b, true);
+  }
+  const hipError_t e = bounds_and_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N,
+                                          precision, stack, scratch, s, b);
+  if (e != hipSuccess) return ABF_E_HIP;
+  return range_batch(img, theta, sigma, h, w, pitch, N, precision, rflags, stack, out, out_pitch,
+                     s, b);
+}
+
+int abf_fast_fused(int h, int w, int kernel_kind, int rho, int N, int precision) {
+  if (h < 1 || w < 1 || rho < 0 || rho > ABF_RHO_MAX || N < 1 || N > ABF_N_MAX ||
+      !stack_kind_ok(kernel_kind) || !prec_ok(precision))
+    return 0;
+  return abf::fast_fuses(kernel_kind, rho, N, precision == ABF_PREC_MIXED ? 1 : 0) ? 1 : 0;
+}
+
 abf_status abf_fast(const float* img, const float* theta, const float* sigma, int h, int w,
                     long long pitch, int kernel_kind, double sigma_s, int rho, int N,
                     int precision, unsigned flags, void* out, long long out_pitch,
@@ -320,11 +354,8 @@ abf_status abf_fast(const float* img, const float* theta, const float* sigma, in
     return ABF_E_WORKSPACE;
   const size_t sb = abf_stack_bytes(h, w, N, precision);
   char* ws = static_cast<char*>(workspace);
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  const hipError_t e = bounds_and_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N,
-                                          precision, ws, ws + sb, s, abf::Batch());
-  if (e != hipSuccess) return ABF_E_HIP;
-  return range_batch(img, theta, sigma, h, w, pitch, N, precision, flags, ws, out, out_pitch, s,
+  return fast_stages(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N, precision,
+                     flags, ws, ws + sb, out, out_pitch, static_cast<hipStream_t>(stream),
                      abf::Batch());
 }
 
@@ -475,12 +506,10 @@ abf_status abf_fast_batched(const abf_request* reqs, int n, int precision, unsig
     b.n = (int)groups[g].size();
     b.tab = dev_tab + first[g];
     b.host_tab = host.data() + first[g];
-    const hipError_t e =
-        bounds_and_moments(r.img, r.h, r.w, r.pitch, r.kernel_kind, r.sigma_s, r.rho, r.N,
-                           precision, base, base + abf_stack_bytes(r.h, r.w, r.N, precision), s, b);
-    if (e != hipSuccess) return ABF_E_HIP;
-    const abf_status st = range_batch(r.img, r.theta, r.sigma, r.h, r.w, r.pitch, r.N, precision,
-                                      flags, base, r.out, r.out_pitch, s, b);
+    const abf_status st = fast_stages(r.img, r.theta, r.sigma, r.h, r.w, r.pitch, r.kernel_kind,
+                                      r.sigma_s, r.rho, r.N, precision, flags, base,
+                                      base + abf_stack_bytes(r.h, r.w, r.N, precision), r.out,
+                                      r.out_pitch, s, b);
     if (st != ABF_OK) return st;
   }
   return ABF_OK;
@@ -517,11 +546,8 @@ abf_status abf_fast_strided(const float* img, const float* theta, const float* s
   b.img = n > 1 ? image_stride : 0;
   b.stack = n > 1 ? (long long)sb : 0;
   b.out = n > 1 ? out_image_stride : 0;
-  const hipError_t e = bounds_and_moments(img, h, w, pitch, kernel_kind, sigma_s, rho, N,
-                                          precision, base, scratch, s, b);
-  if (e != hipSuccess) return ABF_E_HIP;
-  return range_batch(img, theta, sigma, h, w, pitch, N, precision, flags, base, out, out_pitch, s,
-                     b);
+  return fast_stages(img, theta, sigma, h, w, pitch, kernel_kind, sigma_s, rho, N, precision,
+                     flags, base, scratch, out, out_pitch, s, b);
 }
 
 // shared checks of the strided map entry points

@@ -33,6 +33,7 @@
 // (O(R) per pixel), at least 64 output columns wide for every radius up to
 // ABF_RHO_MAX. With unit weights it also serves the FP64 box path at
 // N >= 7, where the box kernel's running sums are not accurate enough.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 
@@ -1555,23 +1556,45 @@ bool gauss_on_mfma(int R, int N, long long h, long long w) {
   return R <= kMfmaRMax && R >= 8 && N <= 6 && h * w >= (1LL << 22);
 }
 
+}  // namespace
+
+// abf_fast's path for the box kernel on the mixed path at small radii: the
+// moment and range stages fused in one kernel (the moments stay in
+// registers), measured faster on MI355X at rho = 5, N = 5..8 (4096^2, two
+// images in flight: 0.85-0.95 of the stack path's time per image) and
+// slower at rho = 20 (1.01-1.05). Elsewhere the stack path.
+bool fast_fuses(int kernel_kind, int rho, int N, int prec) {
+  return kernel_kind == 0 && prec == 1 && N >= 1 && rho <= kFuseRhoMax;
+}
+
+namespace {
+
 template <int N, typename TS>
 hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int kind,
                             double sigma_s, int R, float* alpha, float* beta,
                             long long sp, TS* mom, long long plane, hipStream_t stream,
                             const Batch& b, const FuseSpec* fs, bool bounds) {
   if (bounds && (fs || !moments_take_bounds(kind, R, N, h, w))) return hipErrorNotSupported;
-  // resident waves of the box kernel on this device (occupancy x CUs); the
-  // segment geometry depends on the image and device only (not on the batch
-  // size), so an image gets bit-identical moments alone or in a batch
-  static const long long capacity = [] {
+  // resident waves of the box kernel on this device (occupancy x CUs). The
+  // segment geometry depends on the image, radius and device only (not on
+  // the batch size or on fusion), so an image gets bit-identical moments
+  // alone, in a batch or fused with the range stage. Where abf_fast fuses
+  // the stages it is sized for the lower of the stack and fused
+  // instantiations' occupancies, so the fused kernel runs no partly filled
+  // second round of waves; elsewhere for the stack kernel's own.
+  auto occupancy = [](const void* fn) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, moments_box<N, TS, false>,
-                                                     kBoxWaves * kWave, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBoxWaves * kWave, 0) !=
             hipSuccess || blocks < 1)
       blocks = 8;
     return (long long)blocks * kBoxWaves * device_cus();
-  }();
+  };
+  static const long long cap_stack =
+      occupancy(reinterpret_cast<const void*>(moments_box<N, TS, false>));
+  static const long long cap_both = std::min(
+      cap_stack, occupancy(reinterpret_cast<const void*>(moments_box<N, TS, true>)));
+  const long long capacity =
+      fast_fuses(kind, R, N, sizeof(TS) == 4 ? 1 : 0) ? cap_both : cap_stack;
   const StripGeom g = make_geom(h, w, R, capacity);
   // largest tolerated shift amplification rho^N before a pixel is taken
   // about another origin (or recomputed): the FP32 stack only needs to stay

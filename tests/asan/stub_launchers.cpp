@@ -109,6 +109,10 @@ size_t recursive_scratch_bytes(int h, int w, int N) {
   return 256 + 1792 + (size_t)2 * N * (size_t)h * (size_t)w * sizeof(double);
 }
 
+bool fast_fuses(int kernel_kind, int rho, int N, int prec) {
+  return kernel_kind == 0 && prec == 1 && N >= 1 && rho <= kFuseRhoMax;
+}
+
 bool moments_fusable(int kernel_kind, int rho, int N, long long, long long) {
   return N >= 1 && N <= 8 && (kernel_kind == 0 || rho <= 40);
 }

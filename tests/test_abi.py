@@ -120,6 +120,23 @@ def test_stack_single_pass_query():
     assert L.abf_stack_single_pass(16, 16, 5, 3, 6) == 0
 
 
+def test_fast_fused_query():
+    """abf_fast_fused: the box kernel on the mixed path at rho <= 8 runs the
+    moment and range stages fused; everything else, and invalid arguments,
+    the stack path."""
+    L = abf.lib()
+    assert L.abf_fast_fused(4096, 4096, 0, 5, 8, 1) == 1
+    assert L.abf_fast_fused(4096, 4096, 0, 8, 5, 1) == 1
+    assert L.abf_fast_fused(4096, 4096, 0, 9, 5, 1) == 0
+    assert L.abf_fast_fused(4096, 4096, 0, 5, 8, 0) == 0          # FP64
+    assert L.abf_fast_fused(4096, 4096, 1, 5, 8, 1) == 0          # Gaussian
+    assert L.abf_fast_fused(4096, 4096, 2, 5, 8, 1) == 0          # recursive
+    assert L.abf_fast_fused(64, 64, 0, 3, 0, 1) == 0              # N = 0: bounds only
+    assert L.abf_fast_fused(0, 64, 0, 3, 5, 1) == 0
+    assert L.abf_fast_fused(64, 64, 0, 3, 5, 2) == 0
+    assert abf.fast_fused(64, 64, "box", 3, 5) and not abf.fast_fused(64, 64, "box", 3, 5, "fp64")
+
+
 def test_stack_kernel_query():
     """abf_stack_kernel names the moment kernel of a configuration: box
     running sums, the tile kernel (LDS stride 160 or 256) or the matrix-core
