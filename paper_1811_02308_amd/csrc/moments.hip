@@ -192,6 +192,29 @@ __device__ __forceinline__ void finish_pixel(const double (&m)[N + 1], float a, 
   }
 }
 
+// finish_pixel's fused path for a pixel of a wave-uniform row, theta and
+// sigma already loaded: stores through buffer resources (row bases in
+// scalar registers, the lane's 32-bit byte offset xb); the same values.
+template <int N, typename TS>
+__device__ __forceinline__ void fused_pixel(const double (&m)[N + 1], float a, float b, float th,
+                                            float sg, TS* __restrict__ mrow, long long plane,
+                                            unsigned xb, BufRsrc orow, const FuseArgs& fz) {
+  if (fz.keep_stack) {
+#pragma unroll
+    for (int k = 1; k <= N; ++k) buf_st(buf_rsrc(mrow + (k - 1) * plane), xb, TS(m[k]));
+  }
+  if (a == b) {
+    buf_st(orow, xb, TS(a));
+    return;
+  }
+  double ak[N + 1];                    // a~_k as stored in the stack
+  ak[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= N; ++k) ak[k] = (double)TS(m[k]);
+  buf_st(orow, xb, TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)th, (double)sg, fz.flags,
+                                                     fz.gl)));
+}
+
 // Direct evaluation of a~_k = sum_j omega_j P_k(z_j) for one pixel (y, x),
 // z_j = (f(i-j) - mid) / half, by the whole wave: lanes split the window's
 // taps, each evaluates P_1..P_N by the three-term recurrence, and the
@@ -502,6 +525,12 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
   for (int y = y0; y < y1; ++y) {
     float pa[kChunks], pb[kChunks];
     load_bounds_row(alpha, beta, sp, y, xo, g.O, W, lane, pa, pb);
+    // fused: the row's theta (or f) and sigma as well, issued with the
+    // bounds so that their latency overlaps the row's sums and scan
+    float pt[kChunks], ps[kChunks];
+    if (FUSED) {
+      load_bounds_row(fz.theta, fz.sigma, fz.tpitch, y, xo, g.O, W, lane, pt, ps);
+    }
     if (y > y0) {
       float ci[kV], co[kV];
 #pragma unroll
@@ -565,7 +594,10 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
       }
       if (valid && !bad) {
         if (FUSED) {
-          finish_pixel<N, TS, FUSED>(m, a, b, y, x, (long long)y * sp + x, mom, plane, fz);
+          const float th = q == 0 ? pt[0] : q == 1 ? pt[1] : q == 2 ? pt[2] : pt[3];
+          const float sg = q == 0 ? ps[0] : q == 1 ? ps[1] : q == 2 ? ps[2] : ps[3];
+          fused_pixel<N, TS>(m, a, b, th, sg, mrow, plane, (unsigned)x * (unsigned)sizeof(TS),
+                             buf_rsrc(static_cast<TS*>(fz.out) + (long long)y * fz.opitch), fz);
         } else {
           // the row's plane bases are wave-uniform: buffer resources in
           // scalar registers, one 32-bit byte offset per lane

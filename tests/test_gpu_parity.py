@@ -434,6 +434,22 @@ def test_fused_equals_stack_path(torch, abf, precision, kernel, R, N):
         assert torch.equal(p, q)
 
 
+@pytest.mark.parametrize("R,N", [(5, 8), (8, 6), (3, 5)])
+def test_fused_default_equals_stack_path_4096(torch, abf, vor4096, R, N):
+    """At 4096^2 the box kernel's segment geometry fills the device in whole
+    rounds of waves; where abf_fast takes the fused path (mixed, rho <= 8)
+    the geometry is sized for both instantiations, so abf_fast's output
+    equals the stack path's bit for bit on a full-size image too."""
+    assert abf.fast_fused(4096, 4096, "box", R, N, "mixed")
+    sg = smooth_field(np.random.default_rng(R * 10 + N), 4096, 4096, 10, 40)
+    img, sgd = dev(torch, vor4096), dev(torch, sg)
+    out = abf.fast(img, sgd, kernel="box", rho=R, N=N, precision="mixed")
+    st = abf.moment_stack(img, kernel="box", rho=R, N=N, precision="mixed")
+    ref = abf.range_from_stack(st, sgd, img=img, N=N, precision="mixed")
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("R,N", [(12, 8), (8, 5), (16, 6)])
 def test_fast_gaussian_large_image_sampled(torch, abf, precision, R, N):
