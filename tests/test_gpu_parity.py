@@ -434,6 +434,31 @@ def test_fused_equals_stack_path(torch, abf, precision, kernel, R, N):
         assert torch.equal(p, q)
 
 
+FUSED_EDGE = [((1, 1), 0, 1), ((1, 1), 8, 8), ((1, 300), 5, 6), ((300, 1), 5, 6), ((5, 7), 8, 8),
+              ((70, 90), 0, 6), ((70, 90), 1, 7), ((257, 513), 8, 1), ((64, 250), 4, 5)]
+
+
+@pytest.mark.parametrize("shape,R,N", FUSED_EDGE)
+def test_fused_default_edges(torch, abf, shape, R, N):
+    """abf_fast's fused path (box kernel, mixed, rho <= 8) on single pixels,
+    single rows and columns, rho = 0 and 1, N = 1, and strips with a partial
+    last chunk: equal to the stack path bit for bit, and within the mixed
+    bar of the oracle at every pixel."""
+    h, w = shape
+    assert abf.fast_fused(h, w, "box", R, N, "mixed")
+    f = rect_scene(700 + R + N, h, w, n_rect=4, noise=9.0, side_lo=1, side_hi=max(2, min(h, w)))
+    sg = smooth_field(np.random.default_rng(R + 3 * N), h, w, 6, 45)
+    th = (f + smooth_field(np.random.default_rng(N), h, w, -12, 12)).astype(np.float32)
+    img, sgd, thd = dev(torch, f), dev(torch, sg), dev(torch, th)
+    out = abf.fast(img, sgd, theta=thd, kernel="box", rho=R, N=N, precision="mixed")
+    st = abf.moment_stack(img, kernel="box", rho=R, N=N, precision="mixed")
+    ref = abf.range_from_stack(st, sgd, img=img, theta=thd, N=N, precision="mixed")
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    want = oracle.fast_abf(f, th, sg, "box", R, N)
+    assert np.max(np.abs(out.cpu().numpy().astype(np.float64) - want)) < TOL["mixed"]
+
+
 @pytest.mark.parametrize("R,N", [(5, 8), (8, 6), (3, 5)])
 def test_fused_default_equals_stack_path_4096(torch, abf, vor4096, R, N):
     """At 4096^2 the box kernel's segment geometry fills the device in whole
