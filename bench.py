@@ -107,12 +107,14 @@ def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
 
 # The sources each timed stage's kernel is compiled from (its own file and
 # the headers that file includes).
+_MOMENT_SOURCES = ("moments.hip", "moments_common.h", "range_eval.h", "erfcx_weideman.h",
+                   "abf_internal.h")
 STAGE_SOURCES = {
     "minmax": ("minmax.hip", "abf_internal.h"),
-    "moments": ("moments.hip", "range_eval.h", "abf_internal.h"),
-    "stack": ("moments.hip", "range_eval.h", "abf_internal.h"),
-    "moments_range": ("moments.hip", "range_eval.h", "abf_internal.h"),
-    "range": ("range.hip", "range_eval.h", "abf_internal.h"),
+    "moments": _MOMENT_SOURCES,
+    "stack": _MOMENT_SOURCES,
+    "moments_range": _MOMENT_SOURCES,
+    "range": ("range.hip", "range_eval.h", "erfcx_weideman.h", "abf_internal.h"),
 }
 
 

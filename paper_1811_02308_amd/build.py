@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libabf.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "minmax.hip", "moments.hip", "range.hip", "brute.hip", "sigma.hip",
-           "maps.hip", "noalloc.hip", "batch.hip"]
+           "maps.hip", "noalloc.hip", "batch.hip", "recursive.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

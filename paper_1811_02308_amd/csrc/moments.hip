@@ -38,6 +38,7 @@
 #include <complex>
 
 #include "abf_internal.h"
+#include "moments_common.h"
 #include "range_eval.h"
 
 namespace abf {
@@ -55,11 +56,6 @@ constexpr int kSlotStride = kWave + 4;
 constexpr int kStripSlots = kV * kSlotStride;
 __device__ __forceinline__ int pidx(int e) { return (e & (kV - 1)) * kSlotStride + (e >> 2); }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // v + (value of v `ctrl` DPP positions away), 0 where the source lane is
 // outside its row (row shifts: the lane reads 0 by the bound control, so no
@@ -96,224 +92,6 @@ __device__ __forceinline__ double wave_inclusive_scan(double v, int lane) {
   v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 -> rows 1, 3
   v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 -> rows 2, 3
   return v;
-}
-
-// Per-pixel epilogue: m[1..N] are the window moments of u = f - c (m[0] = 1).
-// Computes a~_1..a~_N into m[1..N] and returns false, or returns true when
-// the binomial shift is too ill-conditioned for the requested precision
-// (the caller then recomputes the pixel directly). alpha == beta gives 0s.
-template <int N>
-__device__ __forceinline__ bool legendre_from_moments(double (&m)[N + 1], float a, float b,
-                                                      double c, double cond_max) {
-  constexpr LegTable LT{};
-  if (a == b) {
-#pragma unroll
-    for (int k = 1; k <= N; ++k) m[k] = 0.0;
-    return false;
-  }
-  const double mid = 0.5 * ((double)a + (double)b) - c;
-  const double half = 0.5 * ((double)b - (double)a);
-  const double ih = rcp(half);      // (a few ulp; a scale, not an exact quantity)
-  // The shift below amplifies the rounding of m_r by about
-  // rho^k, rho = (|mid| + half) / half.
-  const double rho = fma(fabs(mid), ih, 1.0);
-  double rn = rho;
-#pragma unroll
-  for (int k = 1; k < N; ++k) rn *= rho;
-  if (!(rn <= cond_max)) return true;
-  // binomial shift of the moments to the origin mid (Prop. 3):
-  // nu_k = sum_r C(k, r) (-mid)^(k-r) m_r, by repeated synthetic steps
-  const double s = -mid;
-#pragma unroll
-  for (int j = 0; j < N; ++j)
-#pragma unroll
-    for (int k = N; k > j; --k) m[k] = fma(s, m[k - 1], m[k]);
-  // scale to z in [-1, 1]
-  double sc = ih;
-#pragma unroll
-  for (int k = 1; k <= N; ++k) {
-    m[k] *= sc;
-    sc *= ih;
-  }
-  // Legendre moments a~_k = sum_r L[k][r] nu_r (only r = k, k-2, ... are non-zero)
-  double out[N + 1];
-#pragma unroll
-  for (int k = 1; k <= N; ++k) {
-    double acc = 0.0;
-#pragma unroll
-    for (int r = k; r >= 0; r -= 2) acc = fma(LT.L[k][r], m[r], acc);
-    out[k] = acc;
-  }
-#pragma unroll
-  for (int k = 1; k <= N; ++k) m[k] = out[k];
-  return false;
-}
-
-// Fused range stage: theta (or f), sigma, the output and the quadrature rule
-// for kernels that finish each pixel's filter right after its moments
-// (the range half of Algorithm 1 in registers). keep_stack also stores the
-// moments in the stack.
-struct FuseArgs {
-  const float* theta;
-  const float* sigma;
-  long long tpitch;
-  void* out;
-  long long opitch;
-  unsigned flags;
-  int keep_stack;
-  GLArgs gl;
-};
-
-// Completes pixel (y, x) from its Legendre moments m[1..N]: stores them
-// (stack path, or fused with keep_stack) and, when fused, evaluates the
-// range stage and writes the output. The moments enter the range stage
-// rounded to the stack's type, so the fused result equals the stack path's.
-template <int N, typename TS, bool FUSED>
-__device__ __forceinline__ void finish_pixel(const double (&m)[N + 1], float a, float b, int y,
-                                             int x, long long idx, TS* __restrict__ mom,
-                                             long long plane, const FuseArgs& fz) {
-  if (!FUSED || fz.keep_stack) {
-#pragma unroll
-    for (int k = 1; k <= N; ++k) mom[(k - 1) * plane + idx] = TS(m[k]);
-  }
-  if (FUSED) {
-    TS* o = static_cast<TS*>(fz.out) + (long long)y * fz.opitch + x;
-    if (a == b) {
-      *o = TS(a);
-    } else {
-      double ak[N + 1];                  // a~_k as stored in the stack
-      ak[0] = 1.0;
-#pragma unroll
-      for (int k = 1; k <= N; ++k) ak[k] = (double)TS(m[k]);
-      const long long ti = (long long)y * fz.tpitch + x;
-      *o = TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)fz.theta[ti], (double)fz.sigma[ti],
-                                              fz.flags, fz.gl));
-    }
-  }
-}
-
-// finish_pixel's fused path for a pixel of a wave-uniform row, theta and
-// sigma already loaded: stores through buffer resources (row bases in
-// scalar registers, the lane's 32-bit byte offset xb); the same values.
-template <int N, typename TS>
-__device__ __forceinline__ void fused_pixel(const double (&m)[N + 1], float a, float b, float th,
-                                            float sg, TS* __restrict__ mrow, long long plane,
-                                            unsigned xb, BufRsrc orow, const FuseArgs& fz) {
-  if (fz.keep_stack) {
-#pragma unroll
-    for (int k = 1; k <= N; ++k) buf_st(buf_rsrc(mrow + (k - 1) * plane), xb, TS(m[k]));
-  }
-  if (a == b) {
-    buf_st(orow, xb, TS(a));
-    return;
-  }
-  double ak[N + 1];                    // a~_k as stored in the stack
-  ak[0] = 1.0;
-#pragma unroll
-  for (int k = 1; k <= N; ++k) ak[k] = (double)TS(m[k]);
-  buf_st(orow, xb, TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)th, (double)sg, fz.flags,
-                                                     fz.gl)));
-}
-
-// Direct evaluation of a~_k = sum_j omega_j P_k(z_j) for one pixel (y, x),
-// z_j = (f(i-j) - mid) / half, by the whole wave: lanes split the window's
-// taps, each evaluates P_1..P_N by the three-term recurrence, and the
-// partial sums are reduced across the wave. Used for the rare pixels whose
-// shift is ill-conditioned. wts == nullptr means box weights.
-template <int N>
-__device__ __forceinline__ void direct_legendre(const float* __restrict__ img, long long pitch,
-                                                int H, int W, int R, int y, int x, float a,
-                                                float b, const double* __restrict__ wts,
-                                                double norm, int lane, double (&acc)[N + 1]) {
-  const double mid = 0.5 * ((double)a + (double)b);
-  const double ih = 2.0 / ((double)b - (double)a);
-  const int w = 2 * R + 1;
-  const int n = w * w;
-#pragma unroll
-  for (int k = 1; k <= N; ++k) acc[k] = 0.0;
-  for (int t = lane; t < n; t += kWave) {
-    const int dy = t / w - R, dx = t - (t / w) * w - R;
-    const int yy = min(max(y + dy, 0), H - 1), xx = min(max(x + dx, 0), W - 1);
-    const double z = ((double)img[(long long)yy * pitch + xx] - mid) * ih;
-    const double wt = wts ? wts[dy + R] * wts[dx + R] : 1.0;
-    double p0 = 1.0, p1 = z;
-    acc[1] = fma(wt, p1, acc[1]);
-#pragma unroll
-    for (int k = 2; k <= N; ++k) {
-      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-      acc[k] = fma(wt, p2, acc[k]);
-      p0 = p1;
-      p1 = p2;
-    }
-  }
-#pragma unroll
-  for (int k = 1; k <= N; ++k) {
-    double v = acc[k];
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    acc[k] = v * norm;
-  }
-}
-
-// The same sum evaluated by one lane for its own pixel (used when most of a
-// wave's pixels need the recompute, so that all lanes work at once).
-template <int N>
-__device__ __forceinline__ void direct_legendre_lane(const float* __restrict__ img, long long pitch,
-                                                     int H, int W, int R, int y, int x, float a,
-                                                     float b, const double* __restrict__ wts,
-                                                     double norm, double (&acc)[N + 1]) {
-  const double mid = 0.5 * ((double)a + (double)b);
-  const double ih = 2.0 / ((double)b - (double)a);
-#pragma unroll
-  for (int k = 1; k <= N; ++k) acc[k] = 0.0;
-  for (int dy = -R; dy <= R; ++dy) {
-    const float* row = img + (long long)min(max(y + dy, 0), H - 1) * pitch;
-    const double wy = wts ? wts[dy + R] : 1.0;
-    for (int dx = -R; dx <= R; ++dx) {
-      const double z = ((double)row[min(max(x + dx, 0), W - 1)] - mid) * ih;
-      const double wt = wts ? wy * wts[dx + R] : 1.0;
-      double p0 = 1.0, p1 = z;
-      acc[1] = fma(wt, p1, acc[1]);
-#pragma unroll
-      for (int k = 2; k <= N; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-        acc[k] = fma(wt, p2, acc[k]);
-        p0 = p1;
-        p1 = p2;
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 1; k <= N; ++k) acc[k] *= norm;
-}
-
-// Recompute the flagged pixels of a wave: one pixel at a time by the whole
-// wave when few are flagged, every flagged lane its own pixel when many are.
-template <int N, typename TS, bool FUSED>
-__device__ __forceinline__ void recompute_flagged(unsigned long long mask, bool mine, int y, int x,
-                                                  float a, float b, const float* __restrict__ img,
-                                                  long long pitch, int H, int W, int R,
-                                                  const double* __restrict__ wts, double norm,
-                                                  TS* __restrict__ mom, long long plane,
-                                                  long long sp, int lane, const FuseArgs& fz) {
-  if (__popcll(mask) > 24) {
-    if (mine) {
-      double acc[N + 1];
-      direct_legendre_lane<N>(img, pitch, H, W, R, y, x, a, b, wts, norm, acc);
-      finish_pixel<N, TS, FUSED>(acc, a, b, y, x, (long long)y * sp + x, mom, plane, fz);
-    }
-    return;
-  }
-  while (mask) {
-    const int l = __ffsll((long long)mask) - 1;
-    mask &= mask - 1;
-    const int yl = __shfl(y, l, kWave), xl = __shfl(x, l, kWave);
-    const float al = __shfl(a, l, kWave), bl = __shfl(b, l, kWave);
-    double acc[N + 1];
-    direct_legendre<N>(img, pitch, H, W, R, yl, xl, al, bl, wts, norm, lane, acc);
-    if (lane == 0)
-      finish_pixel<N, TS, FUSED>(acc, al, bl, yl, xl, (long long)yl * sp + xl, mom, plane, fz);
-  }
 }
 
 // Window bounds of one output row of a strip, lane `lane` holding output
@@ -628,315 +406,6 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
                                       inv_area, mom, plane, sp, lane, fz);
     }
     wave_sync();
-  }
-}
-
-// ------------------------------------------------------------ recursive kernel
-// Moments for the recursive approximation of the Gaussian (Sec. II-D names
-// recursive filters, Deriche's and Young and van Vliet's, as a way to make the
-// convolutions of Algorithm 1 cost O(1) per pixel for any width): Deriche's
-// fourth-order sum of two damped complex exponentials, g(t) = Re sum_m A_m
-// z_m^|t| (constants in rec_const), taken on the window j in [-R, R] only,
-// so that every weight lies inside the (2R+1)^2 window of alpha_i, beta_i.
-// Per axis, sum_{|j|<=R} g(j) u(x-j) = Re sum_m A_m (q_m(x) + z_m p_m(x)),
-//   causal     q_m(x) = z_m q_m(x-1) + u(x)   - z_m^(R+1) u(x-R-1),
-//   anticausal p_m(x) = z_m p_m(x+1) + u(x+1) - z_m^R     u(x+R+1),
-// the last term removing the sample that leaves the truncated window: O(1)
-// per sample and power. The power sums are taken about one origin c for the
-// image (rec_prep: the mid-range of sampled inputs), since a pass runs along
-// whole rows and columns. rec_rows (a lane per row, a wave per row segment)
-// writes the horizontal sums of (f - c)^k, k = 1..N, as FP64 planes Hk;
-// rec_cols (a lane per column, a wave per column segment) runs the causal
-// vertical recursion down the segment into FP64 planes Ck, then the
-// anticausal one back up, adds the two halves and finishes each pixel with the
-// shift and Legendre change of the other kernels (ill-conditioned pixels,
-// where one origin for the image is far from a narrow window, are recomputed
-// directly from their window with the kernel's weights). A segment starts R
-// samples early (and the anticausal pass R samples late) from a zero state,
-// so every output is the exact truncated sum, whatever the segment length.
-struct RecConst {
-  double zr[2], zi[2];     // poles z_m
-  double ar[2], ai[2];     // A_m
-  double bzr[2], bzi[2];   // A_m z_m (anticausal output)
-  double z1r[2], z1i[2];   // z_m^(R+1)
-  double zRr[2], zRi[2];   // z_m^R
-  double inv_norm2;        // 1 / (sum_{|j|<=R} g(j))^2 (both axes)
-};
-
-// The kernel's normalised 1-D weights g(j) / sum g, j = -R..R, by value.
-struct RecWeights {
-  double v[2 * kRhoMax + 1];
-};
-
-// mid-range of the input on a 64 x 64 grid of samples -> c[0]; the kernel's
-// normalised 1-D weights (for the exact recompute) -> wts[0 .. 2R].
-__global__ __launch_bounds__(256) void rec_prep(const float* __restrict__ img, long long pitch,
-                                                int H, int W, int R, RecWeights w_host,
-                                                double* __restrict__ c, double* __restrict__ wts) {
-  __shared__ float smin[256], smax[256];
-  const FinMinMax fm;
-  float lo = INFINITY, hi = -INFINITY;
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int yy = (int)(((long long)(i >> 6) * (H - 1)) / 63);
-    const int xx = (int)(((long long)(i & 63) * (W - 1)) / 63);
-    const float v = img[(long long)yy * pitch + xx] + 0.0f;
-    lo = fm.min(lo, v);
-    hi = fm.max(hi, v);
-  }
-  smin[threadIdx.x] = lo;
-  smax[threadIdx.x] = hi;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      smin[threadIdx.x] = fm.min(smin[threadIdx.x], smin[threadIdx.x + s]);
-      smax[threadIdx.x] = fm.max(smax[threadIdx.x], smax[threadIdx.x + s]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) c[0] = 0.5 * ((double)smin[0] + (double)smax[0]);
-  for (int j = threadIdx.x; j <= 2 * R; j += 256) wts[j] = w_host.v[j];
-}
-
-// Outputs per row / column segment: every segment pays R warm-up samples
-// in each direction, shorter segments give more waves. Measured at 4096^2,
-// N = 6 (the row pass before its LDS staging): 256 was 5-13% faster than
-// 512 for R = 8..96, 128 and 64 no faster than 256.
-int rec_segment(int R) { (void)R; return 256; }
-constexpr size_t kRecWtsBytes = ((2 * kRhoMax + 1) * sizeof(double) + 255) / 256 * 256;
-
-// Row pass: a wave takes 64 rows (a lane per row) of one row segment. The
-// recursion runs along the row in each lane; the inputs and outputs go
-// through LDS in chunks of kRecCW columns so that every global access is
-// coalesced: the chunk's inputs (u at the entering and at the leaving
-// column of each step) are loaded row-contiguous by the whole wave, and the
-// chunk's N output planes are written (causal pass) or read, added to and
-// written back (anticausal pass) row-contiguous likewise.
-constexpr int kRecCW = 8;                  // columns per staged chunk
-constexpr int kRecLS = kWave + 1;          // LDS stride of a staged column (conflict-free reads)
-
-template <int N>
-__global__ __launch_bounds__(kWave) void rec_rows(const float* __restrict__ img, long long pitch,
-                                                  int H, int W, int R, int seg, RecConst k,
-                                                  const double* __restrict__ cptr,
-                                                  double* __restrict__ hp, long long plane) {
-  __shared__ float tin[kRecCW * kRecLS], tout[kRecCW * kRecLS];
-  __shared__ double tres[N * kRecCW * kRecLS];
-  const int lane = threadIdx.x;
-  const int yb = blockIdx.y * kWave;
-  const int x0 = blockIdx.x * seg, x1 = min(W, x0 + seg);
-  const double c = *cptr;
-  // staging roles: element (row yb + sr + 8 q, column sc) for q = 0..7
-  const int sc = lane % kRecCW, sr = lane / kRecCW;
-  // the inputs of columns xs .. xs + kRecCW - 1 (clamped to the image) into t
-  auto stage = [&](float* t, int xs) {
-    const unsigned xb = (unsigned)min(max(xs + sc, 0), W - 1) * 4u;
-#pragma unroll
-    for (int q = 0; q < kWave / 8; ++q) {
-      const int r = sr + 8 * q;
-      const float* row = img + (long long)min(yb + r, H - 1) * pitch;
-      t[sc * kRecLS + r] = at_byte(row, xb) + 0.0f;
-    }
-  };
-  // the chunk's results: out-of-range rows and columns are not written
-  auto flush = [&](int xs, bool add) {
-    const int x = xs + sc;
-#pragma unroll
-    for (int q = 0; q < kWave / 8; ++q) {
-      const int r = sr + 8 * q;
-      if (x >= x0 && x < x1 && yb + r < H) {
-        double* d = hp + (long long)(yb + r) * W + x;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          const double v = tres[(i * kRecCW + sc) * kRecLS + r];
-          d[i * plane] = add ? d[i * plane] + v : v;
-        }
-      }
-    }
-  };
-  auto powers = [&](float f, double (&p)[N]) {
-    const double u = (double)f - c;
-    double q = u;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      p[i] = q;
-      q *= u;
-    }
-  };
-  double sr_[2][N], si_[2][N];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int i = 0; i < N; ++i) sr_[m][i] = si_[m][i] = 0.0;
-  // causal: x = x0 - R .. x1 - 1, chunk by chunk
-  for (int xs = x0 - R; xs < x1; xs += kRecCW) {
-    stage(tin, xs);
-    stage(tout, xs - R - 1);
-    wave_sync();
-    for (int cc = 0; cc < kRecCW; ++cc) {
-      const int x = xs + cc;
-      double pin[N], pout[N];
-      powers(tin[cc * kRecLS + lane], pin);
-      const bool sub = x > x0;                  // u(x-R-1) was added
-      powers(tout[cc * kRecLS + lane], pout);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        double o = 0.0;
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          double nr = fma(k.zr[m], sr_[m][i], fma(-k.zi[m], si_[m][i], pin[i]));
-          double ni = fma(k.zr[m], si_[m][i], k.zi[m] * sr_[m][i]);
-          if (sub) {
-            nr = fma(-k.z1r[m], pout[i], nr);
-            ni = fma(-k.z1i[m], pout[i], ni);
-          }
-          sr_[m][i] = nr;
-          si_[m][i] = ni;
-          o = fma(k.ar[m], nr, fma(-k.ai[m], ni, o));
-        }
-        tres[(i * kRecCW + cc) * kRecLS + lane] = o;
-      }
-    }
-    wave_sync();
-    flush(xs, false);
-    wave_sync();
-  }
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int i = 0; i < N; ++i) sr_[m][i] = si_[m][i] = 0.0;
-  // anticausal: x = x1 + R - 2 .. x0, chunk by chunk from the right; the
-  // chunk [xs, xs + kRecCW) runs its columns right to left. Its flushes add
-  // to the causal pass's results, which other lanes stored: make those
-  // stores complete and visible first.
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  const int xtop = x1 + R - 2;
-  for (int xe = xtop; xe >= x0; xe -= kRecCW) {
-    const int xs = xe - kRecCW + 1;
-    stage(tin, xs + 1);                         // u(x + 1)
-    stage(tout, xs + R + 1);                    // u(x + R + 1)
-    wave_sync();
-    for (int cc = kRecCW - 1; cc >= 0; --cc) {
-      const int x = xs + cc;
-      double pin[N], pout[N];
-      powers(tin[cc * kRecLS + lane], pin);
-      const bool sub = x <= x1 - 2;             // u(x+R+1) was added
-      powers(tout[cc * kRecLS + lane], pout);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        double o = 0.0;
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          double nr = fma(k.zr[m], sr_[m][i], fma(-k.zi[m], si_[m][i], pin[i]));
-          double ni = fma(k.zr[m], si_[m][i], k.zi[m] * sr_[m][i]);
-          if (sub) {
-            nr = fma(-k.zRr[m], pout[i], nr);
-            ni = fma(-k.zRi[m], pout[i], ni);
-          }
-          sr_[m][i] = nr;
-          si_[m][i] = ni;
-          o = fma(k.bzr[m], nr, fma(-k.bzi[m], ni, o));
-        }
-        tres[(i * kRecCW + cc) * kRecLS + lane] = x > xtop ? 0.0 : o;
-      }
-    }
-    wave_sync();
-    flush(xs, true);
-    wave_sync();
-  }
-}
-
-template <int N, typename TS>
-__global__ __launch_bounds__(kWave) void rec_cols(
-    const float* __restrict__ img, long long pitch, int H, int W, int R, int seg, RecConst k,
-    const double* __restrict__ cptr, const double* __restrict__ wts,
-    const double* __restrict__ hp, double* __restrict__ cp, long long plane,
-    const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
-    TS* __restrict__ mom, long long mplane, double cond_max) {
-  const int lane = threadIdx.x;
-  const int x = blockIdx.x * kWave + lane;
-  const bool live = x < W;
-  const int xc = live ? x : W - 1;
-  const int y0 = blockIdx.y * seg, y1 = min(H, y0 + seg);
-  const double c = *cptr;
-  auto hv = [&](int y, double (&v)[N]) {
-    const double* p = hp + (long long)min(max(y, 0), H - 1) * W + xc;
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = p[i * plane];
-  };
-  double sr[2][N], si[2][N];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int i = 0; i < N; ++i) sr[m][i] = si[m][i] = 0.0;
-  for (int y = y0 - R; y < y1; ++y) {           // causal, down
-    double vin[N], vout[N];
-    hv(y, vin);
-    const bool sub = y > y0;
-    if (sub) hv(y - R - 1, vout);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double o = 0.0;
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        double nr = fma(k.zr[m], sr[m][i], fma(-k.zi[m], si[m][i], vin[i]));
-        double ni = fma(k.zr[m], si[m][i], k.zi[m] * sr[m][i]);
-        if (sub) {
-          nr = fma(-k.z1r[m], vout[i], nr);
-          ni = fma(-k.z1i[m], vout[i], ni);
-        }
-        sr[m][i] = nr;
-        si[m][i] = ni;
-        o = fma(k.ar[m], nr, fma(-k.ai[m], ni, o));
-      }
-      if (y >= y0 && live) cp[(long long)i * plane + (long long)y * W + x] = o;
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int i = 0; i < N; ++i) sr[m][i] = si[m][i] = 0.0;
-  for (int y = y1 + R - 2; y >= y0; --y) {      // anticausal, up, then each pixel
-    double vin[N], vout[N];
-    hv(y + 1, vin);
-    const bool sub = y <= y1 - 2;
-    if (sub) hv(y + R + 1, vout);
-    double m_[N + 1];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double o = 0.0;
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        double nr = fma(k.zr[m], sr[m][i], fma(-k.zi[m], si[m][i], vin[i]));
-        double ni = fma(k.zr[m], si[m][i], k.zi[m] * sr[m][i]);
-        if (sub) {
-          nr = fma(-k.zRr[m], vout[i], nr);
-          ni = fma(-k.zRi[m], vout[i], ni);
-        }
-        sr[m][i] = nr;
-        si[m][i] = ni;
-        o = fma(k.bzr[m], nr, fma(-k.bzi[m], ni, o));
-      }
-      m_[i + 1] = o;
-    }
-    if (y >= y1) continue;
-    bool bad = false;
-    float a = 0.f, b = 0.f;
-    if (live) {
-      const long long idx = (long long)y * sp + x;
-      a = alpha[idx];
-      b = beta[idx];
-      m_[0] = 1.0;
-#pragma unroll
-      for (int i = 0; i < N; ++i)
-        m_[i + 1] = (m_[i + 1] + cp[(long long)i * plane + (long long)y * W + x]) * k.inv_norm2;
-      bad = legendre_from_moments<N>(m_, a, b, c, cond_max);
-      if (!bad) finish_pixel<N, TS, false>(m_, a, b, y, x, idx, mom, mplane, FuseArgs{});
-    }
-    const unsigned long long mask = __ballot(live && bad);
-    if (mask)
-      recompute_flagged<N, TS, false>(mask, live && bad, y, x, a, b, img, pitch, H, W, R, wts, 1.0,
-                                      mom, mplane, sp, lane, FuseArgs{});
   }
 }
 
@@ -1643,8 +1112,6 @@ int device_cus() {
   return cus;
 }
 
-// Shift amplification tolerated by the FP64 path, by degree.
-constexpr double fp64_cond_max(int N) { return N <= 5 ? 1e8 : (N == 6 ? 1e6 : 1e4); }
 
 // The matrix-core kernel is the faster one for wide windows on large
 // images on the mixed path (measured: at 2048^2 and 4096^2 with 8 <= R <= 16
@@ -1787,85 +1254,6 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   return hipErrorInvalidValue;
 }
 
-// Deriche's constants for the Gaussian (order 0), scaled by sigma_s: poles
-// z_m = exp(-(b_m - i w_m) / s), weights A_m = a_m - i a'_m.
-constexpr double kDerA[2] = {1.680, -0.6803}, kDerAp[2] = {3.735, -0.2598};
-constexpr double kDerB[2] = {1.783, 1.723}, kDerW[2] = {0.6318, 1.997};
-
-double rec_sigma(int R, double sigma_s) {
-  const double s = sigma_s > 0 ? sigma_s : R / 3.0;
-  return s > 0 ? s : 1.0;
-}
-
-void rec_setup(int R, double sigma_s, RecConst& k, RecWeights& wt) {
-  const double s = rec_sigma(R, sigma_s);
-  double norm = 0.0;
-  for (int j = -R; j <= R; ++j) {
-    double g = 0.0;
-    for (int m = 0; m < 2; ++m) {
-      const double t = std::fabs((double)j) / s;
-      g += (kDerA[m] * std::cos(kDerW[m] * t) + kDerAp[m] * std::sin(kDerW[m] * t)) *
-           std::exp(-kDerB[m] * t);
-    }
-    wt.v[j + R] = g;
-    norm += g;
-  }
-  for (int j = 0; j <= 2 * R; ++j) wt.v[j] /= norm;
-  for (int m = 0; m < 2; ++m) {
-    const std::complex<double> z = std::exp(std::complex<double>(-kDerB[m], kDerW[m]) / s);
-    const std::complex<double> A(kDerA[m], -kDerAp[m]);
-    const std::complex<double> bz = A * z, z1 = std::pow(z, R + 1), zR = std::pow(z, R);
-    k.zr[m] = z.real();
-    k.zi[m] = z.imag();
-    k.ar[m] = A.real();
-    k.ai[m] = A.imag();
-    k.bzr[m] = bz.real();
-    k.bzi[m] = bz.imag();
-    k.z1r[m] = z1.real();
-    k.z1i[m] = z1.imag();
-    k.zRr[m] = zR.real();
-    k.zRi[m] = zR.imag();
-  }
-  k.inv_norm2 = 1.0 / (norm * norm);
-}
-
-template <int N, typename TS>
-hipError_t launch_rec_t(const float* img, long long pitch, int h, int w, double sigma_s, int R,
-                        const float* alpha, const float* beta, long long sp, TS* mom,
-                        long long plane, void* scratch, hipStream_t stream) {
-  RecConst k;
-  RecWeights wt;
-  rec_setup(R, sigma_s, k, wt);
-  char* base = static_cast<char*>(scratch);
-  double* c = reinterpret_cast<double*>(base);
-  double* wts = reinterpret_cast<double*>(base + 256);
-  double* hp = reinterpret_cast<double*>(base + 256 + kRecWtsBytes);
-  double* cp = hp + (long long)N * h * w;
-  const long long hplane = (long long)h * w;
-  const double cond_max = sizeof(TS) == 4 ? 1e12 : fp64_cond_max(N);
-  hipLaunchKernelGGL(rec_prep, dim3(1), dim3(256), 0, stream, img, pitch, h, w, R, wt, c, wts);
-  const int seg = rec_segment(R);
-  hipLaunchKernelGGL((rec_rows<N>), dim3((w + seg - 1) / seg, (h + kWave - 1) / kWave),
-                     dim3(kWave), 0, stream, img, pitch, h, w, R, seg, k, c, hp, hplane);
-  hipLaunchKernelGGL((rec_cols<N, TS>), dim3((w + kWave - 1) / kWave, (h + seg - 1) / seg),
-                     dim3(kWave), 0, stream, img, pitch, h, w, R, seg, k, c, wts, hp, cp, hplane,
-                     alpha, beta, sp, mom, plane, cond_max);
-  return hipGetLastError();
-}
-
-template <typename TS>
-hipError_t dispatch_rec(int N, const float* img, long long pitch, int h, int w, double sigma_s,
-                        int R, const float* alpha, const float* beta, long long sp, TS* mom,
-                        long long plane, void* scratch, hipStream_t stream) {
-  switch (N) {
-#define ABF_CASE(n) \
-  case n: return launch_rec_t<n, TS>(img, pitch, h, w, sigma_s, R, alpha, beta, sp, mom, plane, scratch, stream);
-    ABF_CASE(1) ABF_CASE(2) ABF_CASE(3) ABF_CASE(4) ABF_CASE(5) ABF_CASE(6) ABF_CASE(7) ABF_CASE(8)
-#undef ABF_CASE
-    default: return hipErrorInvalidValue;
-  }
-}
-
 template <typename TS>
 hipError_t dispatch_n(int N, const float* img, long long pitch, int h, int w, int kind,
                       double sigma_s, int R, float* alpha, float* beta,
@@ -1892,22 +1280,6 @@ hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                               static_cast<double*>(mom), plane_elems, stream, b, fuse, bounds);
   return dispatch_n<float>(N, img, pitch, h, w, kernel_kind, sigma_s, rho, alpha, beta, sp,
                            static_cast<float*>(mom), plane_elems, stream, b, fuse, bounds);
-}
-
-hipError_t launch_recursive_moments(const float* img, long long pitch, int h, int w,
-                                   double sigma_s, int rho, int N, int prec, const float* alpha,
-                                   const float* beta, long long sp, void* mom,
-                                   long long plane_elems, void* scratch, hipStream_t stream) {
-  if (N < 1 || N > kNMax || rho < 0 || rho > kRhoMax) return hipErrorInvalidValue;
-  if (prec == 0)
-    return dispatch_rec<double>(N, img, pitch, h, w, sigma_s, rho, alpha, beta, sp,
-                                static_cast<double*>(mom), plane_elems, scratch, stream);
-  return dispatch_rec<float>(N, img, pitch, h, w, sigma_s, rho, alpha, beta, sp,
-                             static_cast<float*>(mom), plane_elems, scratch, stream);
-}
-
-size_t recursive_scratch_bytes(int h, int w, int N) {
-  return 256 + kRecWtsBytes + (size_t)2 * N * (size_t)h * (size_t)w * sizeof(double);
 }
 
 bool moments_take_bounds(int kernel_kind, int rho, int N, long long h, long long w) {

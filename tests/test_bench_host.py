@@ -44,12 +44,13 @@ def test_traffic_lookup_follows_the_sources(tmp_path, monkeypatch):
     root = tmp_path / "repo"
     csrc = root / "paper_1811_02308_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for name in ("moments.hip", "range_eval.h", "abf_internal.h", "range.hip", "minmax.hip"):
+    for name in {n for srcs in bench.STAGE_SOURCES.values() for n in srcs}:
         shutil.copy(os.path.join(ROOT, "paper_1811_02308_amd", "csrc", name), csrc / name)
     (root / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(root))
     h = bench.stage_source_hash("stack")
     assert h == bench.stage_source_hash("moments")          # same kernel sources
+    assert h == bench.stage_source_hash("moments_range")
     assert h != bench.stage_source_hash("range")
     table = ("| workload | stage | kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | FETCH scale | "
              "WRITE scale | bytes | source |\n|---|---|---|---|---|---|---|---|---|\n"
@@ -58,7 +59,8 @@ def test_traffic_lookup_follows_the_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("wl", "stack") == 12345
     assert bench.measured_traffic("wl", "range") is None
     assert bench.measured_traffic("other", "stack") is None
-    # any change to the kernel's sources invalidates the reading
-    with open(csrc / "moments.hip", "a") as fh:
+    # any change to the kernel's sources invalidates the reading, the shared
+    # device helpers included
+    with open(csrc / "moments_common.h", "a") as fh:
         fh.write("\n// changed\n")
     assert bench.measured_traffic("wl", "stack") is None
