@@ -469,6 +469,13 @@ def main():
     whole = {"bound": "hbm", "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(path_gbs / HBM_PEAK_GBS, 4), "bytes_per_step": path_bytes,
              "bytes_per_pixel": 16 + 8 * planes}
+    if fuses["mixed"]:
+        # the same rate against the stack formulation's algorithmic bytes (the
+        # whole moment stack written and read once): what the fused path
+        # keeps out of HBM, expressed as a fraction of the HBM roofline
+        sb = 16 + 8 * (N + 2)
+        whole["stack_formulation_bytes_per_pixel"] = sb
+        whole["frac_at_stack_formulation_bytes"] = round(H * W * sb / (ms_m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     lat_m = np.array(tot_m)
     res = {
