@@ -560,7 +560,15 @@ def bench(loads=(0.3, 0.6, 0.9), n=300, warm=30, slots=4, budget_gb=16.0, seed=1
     sat = summarize(res, wall)
     sat_px_s = sat["mpix_per_s"] * 1e6
     mean_px = float(np.mean([r.pixels for r in sat_reqs]))
-    report = {"saturation": sat, "loads": {}, "breakdown": breakdown(sat_reqs, precision)}
+    # the rate as a fraction of the 8 TB/s HBM roofline, at the algorithmic
+    # bytes of the stack formulation of each request (f, theta-or-f, sigma in,
+    # the output out, the N + 2 stack planes written and read once)
+    bpp = (sum(r.pixels * (16 + 8 * (r.N + 2)) for r in sat_reqs) /
+           sum(r.pixels for r in sat_reqs))
+    hbm = lambda mpix_s: round(mpix_s * 1e6 * bpp / 8e12, 4)
+    sat["hbm_roofline_frac"] = hbm(sat["mpix_per_s"])
+    report = {"saturation": sat, "loads": {}, "breakdown": breakdown(sat_reqs, precision),
+              "stack_formulation_bytes_per_pixel": round(bpp, 2)}
     for L in loads:
         rate = L * sat_px_s / mean_px
         reqs = make_requests(seed + int(1000 * L), n + warm, rate, scale=scale)
@@ -568,6 +576,7 @@ def bench(loads=(0.3, 0.6, 0.9), n=300, warm=30, slots=4, budget_gb=16.0, seed=1
         res = srv.run(reqs)
         report["loads"][str(L)] = summarize(res[warm:])
         report["loads"][str(L)]["offered_req_per_s"] = rate
+        report["loads"][str(L)]["hbm_roofline_frac"] = hbm(report["loads"][str(L)]["mpix_per_s"])
     return report
 
 
