@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kWave) void rec_rows(const float* __restrict__ img,
           si_[m][i] = ni;
           o = fma(k.bzr[m], nr, fma(-k.bzi[m], ni, o));
         }
-        tres[(i * kRecCW + cc) * kRecLS + lane] = x > xtop ? 0.0 : o;
+        tres[(i * kRecCW + cc) * kRecLS + lane] = o;
       }
     }
     wave_sync();

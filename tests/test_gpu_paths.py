@@ -208,6 +208,37 @@ def test_texture_full_size_first_pass_sampled(torch, abf, texture, precision):
         assert np.max(np.abs(got - ref)) < TOL[precision], c
 
 
+# ----------------------------------------------------------------- large images
+@pytest.fixture(scope="module")
+def large_image():
+    base = voronoi(1003, 4096, 4096)
+    f = np.ascontiguousarray(np.tile(base, (4, 4))[:12292, :12290])
+    sg = np.ascontiguousarray(np.tile(smooth_field(np.random.default_rng(9), 1024, 1024, 10, 40),
+                                      (13, 13))[:12292, :12290])
+    return f, sg
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_image_sampled(torch, abf, large_image, precision):
+    """A 12292 x 12290 image (151 Mpix; 0.6 GB per float plane, an 11 GB FP64
+    stack at N = 8): the 4096^2 Voronoi scene tiled 3 x 3 plus a ragged
+    border, box R = 5, N = 8 (mixed: the fused path; FP64: the tile
+    kernel), sampled pixels against the oracle, corners and the last rows
+    and columns included. Every index of the kernels beyond 2^31 bytes of a
+    plane's start runs here."""
+    f, sg = large_image
+    h, w = f.shape
+    R, N = 5, 8
+    out = abf.fast(dev(torch, f), dev(torch, sg), kernel="box", rho=R, N=N, precision=precision)
+    torch.cuda.synchronize()
+    ys, xs = edge_samples(h, w, 300, seed=12)
+    got = out[torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].cpu().numpy().astype(np.float64)
+    del out
+    torch.cuda.empty_cache()
+    ref = oracle.fast_abf(f, None, sg, "box", R, N, pixels=(ys, xs))
+    assert np.max(np.abs(got - ref)) < TOL[precision]
+
+
 # ----------------------------------------------------------------- streams
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_non_current_stream(torch, abf, precision):
