@@ -28,17 +28,61 @@ struct FinMinMax {
   __device__ float max(float a, float b) const { return __builtin_amdgcn_fmed3f(a, b, hi); }
 };
 
-// Gauss-Legendre rules on [0, 1] used by the range kernel: 16 nodes for the
+// Gauss-Legendre rules on [0, 1] used by the range stage: 16 nodes for the
 // FP64 path, 12 for the mixed path.
 constexpr int kGLNodes = 16;
 constexpr int kGLNodesMixed = 12;
+
+// cos(x) for 0 <= x <= pi by its Taylor series (terms to x^58/58!, far
+// below FP64 rounding there); only the starting guess of the root search.
+__host__ __device__ constexpr double cos_series(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+
+// Nodes t and weights w of the Q-node rule on [0, 1] (entries beyond Q are
+// 0): the roots z of P_Q by Newton's iteration from the starting guess
+// cos(pi (i + 3/4) / (Q + 1/2)), with the three-term recurrence for P_Q and
+// P_Q' = Q (z P_Q - P_{Q-1}) / (z^2 - 1); mapped by t = (1 - z)/2, weight
+// 1 / ((1 - z^2) P_Q'(z)^2) (half the weight on [-1, 1]). Evaluated at
+// compile time, so kernels take the rule as literal constants.
 struct GLRule {
   double t[kGLNodes];
   double w[kGLNodes];
+  __host__ __device__ constexpr explicit GLRule(int Q) : t{}, w{} {
+    for (int i = 0; i < Q; ++i) {
+      double z = cos_series(3.14159265358979323846 * (i + 0.75) / (Q + 0.5));
+      double p0 = 1.0, p1 = z, dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        p0 = 1.0;
+        p1 = z;
+        for (int k = 2; k <= Q; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = Q * (z * p1 - p0) / (z * z - 1.0);
+        const double dz = p1 / dp;
+        z -= dz;
+        if ((dz < 0.0 ? -dz : dz) < 1e-17) break;
+      }
+      p0 = 1.0;
+      p1 = z;
+      for (int k = 2; k <= Q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = Q * (z * p1 - p0) / (z * z - 1.0);
+      t[i] = 0.5 * (1.0 - z);
+      w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
 };
-// Computed once per node count on the host (Newton iteration on P_Q), see
-// api.cpp. q must be kGLNodes or kGLNodesMixed (entries beyond q are 0).
-const GLRule& gl_rule(int q);
 
 // Coefficients of the Legendre polynomial P_k(z) = sum_r L[k][r] z^r
 // (three-term recurrence (k+1) P_{k+1} = (2k+1) z P_k - k P_{k-1}).

@@ -5,55 +5,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
-#include <mutex>
 #include <vector>
 
 #include "abf_internal.h"
-
-namespace abf {
-
-// Gauss-Legendre nodes/weights on [0,1]: roots of P_Q by Newton iteration
-// from the initial guess cos(pi (i + 3/4) / (Q + 1/2)).
-static void make_rule(GLRule& rule, int Q) {
-  for (int i = 0; i < kGLNodes; ++i) rule.t[i] = rule.w[i] = 0.0;
-  for (int i = 0; i < Q; ++i) {
-    double z = std::cos(M_PI * (i + 0.75) / (Q + 0.5));
-    double dp = 1.0;
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = z;
-      for (int k = 2; k <= Q; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      dp = Q * (z * p1 - p0) / (z * z - 1.0);
-      const double dz = p1 / dp;
-      z -= dz;
-      if (std::fabs(dz) < 1e-17) break;
-    }
-    double p0 = 1.0, p1 = z;
-    for (int k = 2; k <= Q; ++k) {
-      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-      p0 = p1;
-      p1 = p2;
-    }
-    dp = Q * (z * p1 - p0) / (z * z - 1.0);
-    rule.t[i] = 0.5 * (1.0 - z);                 // map [-1,1] -> [0,1]
-    rule.w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // = (2/((1-z^2) P'^2)) / 2
-  }
-}
-
-const GLRule& gl_rule(int q) {
-  static GLRule r16, r12;
-  static std::once_flag once;
-  std::call_once(once, [] {
-    make_rule(r16, kGLNodes);
-    make_rule(r12, kGLNodesMixed);
-  });
-  return q == kGLNodesMixed ? r12 : r16;
-}
-
-}  // namespace abf
 
 namespace {
 

@@ -1186,7 +1186,6 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
     fz.opitch = fs->opitch;
     fz.flags = fs->flags;
     fz.keep_stack = fs->keep_stack;
-    fz.gl = make_gl_args(sizeof(TS) == 4);
   }
   if (kind == 0 && !box_tile) {
     dim3 grid((waves + kBoxWaves - 1) / kBoxWaves, b.n);

@@ -68,10 +68,10 @@ __device__ __forceinline__ bool legendre_from_moments(double (&m)[N + 1], float 
   return false;
 }
 
-// Fused range stage: theta (or f), sigma, the output and the quadrature rule
-// for kernels that finish each pixel's filter right after its moments
-// (the range half of Algorithm 1 in registers). keep_stack also stores the
-// moments in the stack.
+// Fused range stage: theta (or f), sigma and the output for kernels that
+// finish each pixel's filter right after its moments (the range half of
+// Algorithm 1 in registers). keep_stack also stores the moments in the
+// stack.
 struct FuseArgs {
   const float* theta;
   const float* sigma;
@@ -80,7 +80,6 @@ struct FuseArgs {
   long long opitch;
   unsigned flags;
   int keep_stack;
-  GLArgs gl;
 };
 
 // Completes pixel (y, x) from its Legendre moments m[1..N]: stores them
@@ -106,21 +105,25 @@ __device__ __forceinline__ void finish_pixel(const double (&m)[N + 1], float a, 
       for (int k = 1; k <= N; ++k) ak[k] = (double)TS(m[k]);
       const long long ti = (long long)y * fz.tpitch + x;
       *o = TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)fz.theta[ti], (double)fz.sigma[ti],
-                                              fz.flags, fz.gl));
+                                              fz.flags));
     }
   }
 }
 
 // finish_pixel's fused path for a pixel of a wave-uniform row, theta and
-// sigma already loaded: stores through buffer resources (row bases in
-// scalar registers, the lane's 32-bit byte offset xb); the same values.
+// sigma already loaded: the output goes through a buffer resource (row base
+// in scalar registers, the lane's 32-bit byte offset xb); the same values.
+// The stack planes (keep_stack only) take plain stores: eight more buffer
+// resources would hold 32 scalar registers across the row, which the
+// compiler then spills to vector lanes on the default path as well.
 template <int N, typename TS>
 __device__ __forceinline__ void fused_pixel(const double (&m)[N + 1], float a, float b, float th,
                                             float sg, TS* __restrict__ mrow, long long plane,
                                             unsigned xb, BufRsrc orow, const FuseArgs& fz) {
   if (fz.keep_stack) {
+    TS* p = mrow + xb / (unsigned)sizeof(TS);
 #pragma unroll
-    for (int k = 1; k <= N; ++k) buf_st(buf_rsrc(mrow + (k - 1) * plane), xb, TS(m[k]));
+    for (int k = 1; k <= N; ++k, p += plane) *p = TS(m[k]);
   }
   if (a == b) {
     buf_st(orow, xb, TS(a));
@@ -130,8 +133,8 @@ __device__ __forceinline__ void fused_pixel(const double (&m)[N + 1], float a, f
   ak[0] = 1.0;
 #pragma unroll
   for (int k = 1; k <= N; ++k) ak[k] = (double)TS(m[k]);
-  buf_st(orow, xb, TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)th, (double)sg, fz.flags,
-                                                     fz.gl)));
+  buf_st(orow, xb, TS(range_eval<N, sizeof(TS) == 4>(a, b, ak, (double)th, (double)sg,
+                                                     fz.flags)));
 }
 
 // Direct evaluation of a~_k = sum_j omega_j P_k(z_j) for one pixel (y, x),

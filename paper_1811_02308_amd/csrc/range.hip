@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void range_kernel(
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
     const TS* __restrict__ mom, long long plane, const float* __restrict__ theta,
     long long tpitch, const float* __restrict__ sigma, long long spitch, int H, int W,
-    unsigned flags, TO* __restrict__ out, long long opitch, GLArgs gl, Batch bt) {
+    unsigned flags, TO* __restrict__ out, long long opitch, Batch bt) {
   // mixed path: 12-node rule and single-precision exponentials for the
   // quadrature weights (their 1e-7 relative error is far below the FP32
   // output's own resolution of the 0.05 tolerance); FP64 path: 16 nodes.
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void range_kernel(
   for (int k = 1; k <= N; ++k) at[k] = buf_ld(buf_rsrc(mom + (k - 1) * plane + row), bxs, mom);
   const double th = buf_ld_f32(buf_rsrc(theta + (long long)y * tpitch), bx4);
   const double sg = buf_ld_f32(buf_rsrc(sigma + (long long)y * spitch), bx4);
-  buf_st(orow, bxo, TO(range_eval<N, kMixed>(a, b, at, th, sg, flags, gl)));
+  buf_st(orow, bxo, TO(range_eval<N, kMixed>(a, b, at, th, sg, flags)));
 }
 
 
@@ -94,8 +94,7 @@ __global__ __launch_bounds__(256) void uniform_kernel(
     const float* __restrict__ alpha, const float* __restrict__ beta, long long sp,
     const TS* __restrict__ mom1, const float* __restrict__ img, long long ipitch,
     const float* __restrict__ theta, long long tpitch, const float* __restrict__ sigma,
-    long long spitch, int H, int W, unsigned flags, TO* __restrict__ out, long long opitch,
-    GLArgs gl) {
+    long long spitch, int H, int W, unsigned flags, TO* __restrict__ out, long long opitch) {
   constexpr bool kMixed = sizeof(TO) == 4;
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -113,7 +112,7 @@ __global__ __launch_bounds__(256) void uniform_kernel(
   }
   const double ak[1] = {1.0};
   *o = TO(range_eval<0, kMixed>(lo, hi, ak, (double)theta[(long long)y * tpitch + x],
-                                (double)sigma[(long long)y * spitch + x], flags, gl));
+                                (double)sigma[(long long)y * spitch + x], flags));
 }
 
 template <int N, typename TS, typename TO>
@@ -121,11 +120,10 @@ hipError_t launch_t(const float* alpha, const float* beta, long long sp, const v
                     long long plane, const float* theta, long long tpitch, const float* sigma,
                     long long spitch, int h, int w, unsigned flags, void* out, long long opitch,
                     hipStream_t stream, const Batch& b) {
-  const GLArgs gl = make_gl_args(sizeof(TO) == 4);
   dim3 grid((w + 63) / 64, (h + 3) / 4, b.n);
   hipLaunchKernelGGL((range_kernel<N, TS, TO>), grid, dim3(256), 0, stream, alpha, beta, sp,
                      static_cast<const TS*>(mom), plane, theta, tpitch, sigma, spitch, h, w,
-                     flags, static_cast<TO*>(out), opitch, gl, b);
+                     flags, static_cast<TO*>(out), opitch, b);
   return hipGetLastError();
 }
 
@@ -155,15 +153,14 @@ hipError_t launch_range_uniform(const float* alpha, const float* beta, long long
                                 long long spitch, int h, int w, int prec, unsigned flags,
                                 void* out, long long opitch, hipStream_t stream) {
   dim3 grid((w + 63) / 64, (h + 3) / 4);
-  const GLArgs gl = make_gl_args(prec != 0);
   if (prec == 0)
     hipLaunchKernelGGL((uniform_kernel<double, double>), grid, dim3(256), 0, stream, alpha, beta,
                        sp, static_cast<const double*>(mom1), img, ipitch, theta_or_img, tpitch,
-                       sigma, spitch, h, w, flags, static_cast<double*>(out), opitch, gl);
+                       sigma, spitch, h, w, flags, static_cast<double*>(out), opitch);
   else
     hipLaunchKernelGGL((uniform_kernel<float, float>), grid, dim3(256), 0, stream, alpha, beta,
                        sp, static_cast<const float*>(mom1), img, ipitch, theta_or_img, tpitch,
-                       sigma, spitch, h, w, flags, static_cast<float*>(out), opitch, gl);
+                       sigma, spitch, h, w, flags, static_cast<float*>(out), opitch);
   return hipGetLastError();
 }
 

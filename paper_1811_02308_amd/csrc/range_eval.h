@@ -10,21 +10,6 @@
 
 namespace abf {
 
-struct GLArgs {
-  double t[kGLNodes];
-  double w[kGLNodes];
-};
-
-inline GLArgs make_gl_args(bool mixed) {
-  GLArgs gl;
-  const GLRule& r = gl_rule(mixed ? kGLNodesMixed : kGLNodes);
-  for (int q = 0; q < kGLNodes; ++q) {
-    gl.t[q] = r.t[q];
-    gl.w[q] = r.w[q];
-  }
-  return gl;
-}
-
 constexpr double kSqrtPi = 1.7724538509055160273;
 
 // The fit c = A^-1 mu of eq. inv in the Legendre form: p(t) = sum_k (2k+1)
@@ -115,13 +100,14 @@ __device__ __forceinline__ double erfcx_w(double x) {
 // g^ = a + (b - a) F for one pixel and the interval [a, b] (a < b; the
 // window bounds alpha, beta in Algorithm 1). at[k] = a~_k, the Legendre
 // moments, with at[0] = 1; th = theta, sg = sigma at the pixel.
-// kMixed selects the mixed-precision thresholds, node count and FP32
-// quadrature exponentials.
+// kMixed selects the mixed-precision thresholds, the 12-node rule (else 16)
+// and FP32 quadrature exponentials.
 template <int N, bool kMixed>
 __device__ __forceinline__ double range_eval(double a, double b, const double (&at)[N + 1], double th,
-                                             double sg, unsigned flags, const GLArgs& gl) {
+                                             double sg, unsigned flags) {
   constexpr FitTables FT{};
   constexpr int Q = kMixed ? kGLNodesMixed : kGLNodes;
+  constexpr GLRule gl(Q);
   const double da = a, delta = b - da;
   double t0, lam, sl;
   if (kMixed) {
