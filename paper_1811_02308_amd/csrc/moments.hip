@@ -195,12 +195,20 @@ __device__ __forceinline__ bool legendre_from_sums(double (&m)[N + 1], float a, 
   return false;
 }
 
+// Strips 0 .. n_strips-2 are O columns wide and cut into n_segs segments of
+// TH rows; the last strip (the image's remaining columns, possibly far
+// fewer) into n_segs_last segments of TH_last rows, so that its waves carry
+// about as much work as the others. Waves: the full strips' segments
+// (strip-major within a segment row), then the last strip's.
 struct StripGeom {
   int O;       // output columns per strip
   int Rpad;    // R rounded up to a multiple of kV
   int TH;      // output rows per segment
   int n_strips;
   int n_segs;
+  int TH_last;
+  int n_segs_last;
+  __host__ __device__ int waves() const { return (n_strips - 1) * n_segs + n_segs_last; }
 };
 
 // Slot of the exclusive prefix P(-1) = 0 in each power's LDS row (pidx(-1):
@@ -238,13 +246,17 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
   // scalar values)
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int gw = blockIdx.x * kBoxWaves + wv;
-  if (gw >= g.n_strips * g.n_segs) return;
+  if (gw >= g.waves()) return;
   const FinMinMax fm;
-  const int strip = gw % g.n_strips;
-  const int seg = gw / g.n_strips;
-  const int y0 = seg * g.TH;
-  const int y1 = min(H, y0 + g.TH);
+  const int n_full = (g.n_strips - 1) * g.n_segs;
+  const bool last = gw >= n_full;
+  const int fs = max(g.n_strips - 1, 1);
+  const int strip = last ? g.n_strips - 1 : gw % fs;
+  const int th = last ? g.TH_last : g.TH;
+  const int y0 = (last ? gw - n_full : gw / fs) * th;
+  const int y1 = min(H, y0 + th);
   const int xo = strip * g.O;            // first output column of the strip
+  const int ow = min(g.O, W - xo);       // its output columns
   const int xs = xo - g.Rpad;            // padded column 0
   const double c = input_origin(img, pitch, y0, y1, xo, g.O, W, lane, fm);
   double (*const shw)[kStripSlots] = sh[wv];
@@ -388,11 +400,11 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
     };
     if (FUSED) {
       for (int q = 0; q < kChunks; ++q)
-        if (q * kWave < g.O) chunk(q);
+        if (q * kWave < ow) chunk(q);
     } else {
 #pragma unroll
       for (int q = 0; q < kChunks; ++q)
-        if (q * kWave < g.O) chunk(q);
+        if (q * kWave < ow) chunk(q);
     }
     for (int q = 0; q < kChunks; ++q) {
       const bool mine = (badq >> q) & 1u;
@@ -1080,24 +1092,42 @@ int gauss_tile_tx(int R, int N) {
 // segments should be long; but the grid should also fill the device in
 // whole rounds (a last, partly filled round of waves idles most CUs). The
 // height is the smallest that makes all waves fit in `capacity` resident
-// waves (one round), else two rounds, ..., capped at 64 rows.
-StripGeom make_geom(int H, int W, int R, long long capacity) {
+// waves (one round), else two rounds, ..., capped at 64 rows. The last
+// strip's rows cost (ve + its chunks) / (ve + a full strip's chunks) of a
+// full strip's, ve being the cost of a row's vertical update and scan in
+// units of one 64-column chunk of the row's epilogue (from instruction
+// counts: about 0.8 with the fused range stage, about 3 without); its
+// segments are taller by that factor (at most 64 rows as well).
+StripGeom make_geom(int H, int W, int R, long long capacity, double ve) {
   StripGeom g;
   g.Rpad = (R + kV - 1) / kV * kV;
   g.O = (kStrip - R - g.Rpad) / kV * kV;
   g.n_strips = (W + g.O - 1) / g.O;
-  int th = 64;
+  const int o_last = W - (g.n_strips - 1) * g.O;
+  double r = g.n_strips == 1 ? 1.0
+                              : (ve + (o_last + kWave - 1) / kWave) /
+                                    (ve + (g.O + kWave - 1) / kWave);
+  // (balance only a grid that fills the device: with fewer waves than
+  // resident slots the kernel lasts as long as its slowest wave, and
+  // shorter segments always help)
+  const bool balance = (long long)g.n_strips * ((H + 1) / 2) > capacity / 2;
+  if (!balance) r = 1.0;
+  const double units = (g.n_strips - 1) + r;
+  auto fit = [&](int th, long long budget) {
+    g.TH = th;
+    g.n_segs = (H + th - 1) / th;
+    g.TH_last = std::min(64, std::max(th, (int)(th / r)));
+    g.n_segs_last = (H + g.TH_last - 1) / g.TH_last;
+    return g.waves() <= budget;
+  };
   for (long long m = 1; m <= 64; ++m) {
-    const long long segs = m * capacity / g.n_strips;
+    const long long budget = m * capacity;
+    const long long segs = (long long)(budget / units);
     if (segs < 1) continue;
-    const long long t = (H + segs - 1) / segs;
-    if (t <= 64) {
-      th = (int)(t < 2 ? 2 : t);
-      break;
-    }
+    for (int th = std::max(2LL, (H + segs - 1) / segs); th <= 64; ++th)
+      if (fit(th, budget)) return g;
   }
-  g.TH = th;
-  g.n_segs = (H + th - 1) / th;
+  fit(64, 0);
   return g;
 }
 
@@ -1160,9 +1190,8 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
       occupancy(reinterpret_cast<const void*>(moments_box<N, TS, false>));
   static const long long cap_both = std::min(
       cap_stack, occupancy(reinterpret_cast<const void*>(moments_box<N, TS, true>)));
-  const long long capacity =
-      fast_fuses(kind, R, N, sizeof(TS) == 4 ? 1 : 0) ? cap_both : cap_stack;
-  const StripGeom g = make_geom(h, w, R, capacity);
+  const bool fused_geom = fast_fuses(kind, R, N, sizeof(TS) == 4 ? 1 : 0);
+  const StripGeom g = make_geom(h, w, R, fused_geom ? cap_both : cap_stack, fused_geom ? 0.8 : 3.0);
   // largest tolerated shift amplification rho^N before a pixel is taken
   // about another origin (or recomputed): the FP32 stack only needs to stay
   // below its own rounding; the FP64 path's 1e-6 bound was checked pixel
@@ -1170,7 +1199,7 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
   // shift's rounding (amplified further by the Legendre coefficients, which
   // grow with N) needed rho^N <= 1e4 at N = 8
   const double cond_max = sizeof(TS) == 4 ? 1e12 : fp64_cond_max(N);
-  const int waves = g.n_strips * g.n_segs;
+  const int waves = g.waves();
   // The box kernel's running sums add and remove every row of a strip
   // segment, so their rounding follows the largest values the strip holds,
   // not the pixel's window: too much for the FP64 path at N >= 7 on
