@@ -87,14 +87,24 @@ __device__ __forceinline__ double rcp(double x) {
 // (coefficients from gen_erfcx.py). Relative error below 1.3e-15 for
 // finite x >= 0 (checked against 40-digit values), tending to the
 // function's own limit 1/(sqrt(pi) x). About 45 instructions, against
-// about 130 for the library's erfcx (used by the FP64 path).
-__device__ __forceinline__ double erfcx_w(double x) {
-  const double r = rcp(kErfcxL + x);
+// about 130 for the library's erfcx (used by the FP64 path). This takes r;
+// erfcx_w2 below forms it.
+__device__ __forceinline__ double erfcx_w_r(double r) {
   const double z = fma(2.0 * kErfcxL, r, -1.0);
   double p = kErfcxA[0];
 #pragma unroll
   for (int n = 1; n < kErfcxTerms; ++n) p = fma(p, z, kErfcxA[n]);
   return r * fma(2.0 * r, p, 0.56418958354775628695);     // 1/sqrt(pi)
+}
+
+// erfcx at two arguments x0, x1 >= 0, with one reciprocal for both r = 1/(L + x):
+// 1/(u v) times v and times u (a few ulp, far below the expansion's error;
+// u v stays finite for every argument the range stage passes).
+__device__ __forceinline__ void erfcx_w2(double x0, double x1, double& e0, double& e1) {
+  const double u = kErfcxL + x0, v = kErfcxL + x1;
+  const double ruv = rcp(u * v);
+  e0 = erfcx_w_r(v * ruv);
+  e1 = erfcx_w_r(u * ruv);
 }
 
 // g^ = a + (b - a) F for one pixel and the interval [a, b] (a < b; the
@@ -131,7 +141,9 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
 
   const double ts = fmin(fmax(t0, 0.0), 1.0);
   const double dist = fabs(t0 - ts);
-  double T1, T2, F0;
+  // T1, T2 and the N = 0 estimate's ratio f0n / f0d, which is evaluated
+  // only where the fit's ratio fails
+  double T1, T2, f0n, f0d;
   if (lam >= lam_split(N, kMixed) && dist * sl < outside_limit(kMixed)) {
     double c[N + 1];
 #pragma unroll
@@ -156,14 +168,25 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
     // (the mixed path takes the shorter expansion: measured 7% faster there,
     // with a margin of ~1e3 to the mixed tolerance; the FP64 path keeps the
     // library function's last ulps)
-    const double X0 = (kMixed ? erfcx_w(fabs(A)) : erfcx(fabs(A))) * E0;
-    const double X1 = (kMixed ? erfcx_w(fabs(B)) : erfcx(fabs(B))) * E1;
+    double X0, X1;
+    if (kMixed) {
+      erfcx_w2(fabs(A), fabs(B), X0, X1);
+    } else {
+      X0 = erfcx(fabs(A));
+      X1 = erfcx(fabs(B));
+    }
+    X0 *= E0;
+    X1 *= E1;
     const bool straddle = A <= 0.0 && B >= 0.0;
     const double diff = (straddle ? 2.0 - X1 : (A > 0.0 ? -X1 : X1)) + (A > 0.0 ? X0 : -X0);
-    const double i2l = 0.5 * rcp(lam);
-    double Im2 = 0.5 * kSqrtPi * rcp(sl) * diff;     // I_0
+    // (mixed path: lambda is the exact square of sqrt(lambda), so 1/lambda
+    // is taken as (1/sqrt(lambda))^2, one reciprocal instead of two)
+    const double isl = rcp(sl);
+    const double i2l = kMixed ? 0.5 * (isl * isl) : 0.5 * rcp(lam);
+    double Im2 = 0.5 * kSqrtPi * isl * diff;         // I_0
     double Im1 = fma(t0, Im2, (E0 - E1) * i2l);      // I_1
-    F0 = Im1 * rcp(Im2);
+    f0n = Im1;
+    f0d = Im2;
     T2 = c[0] * Im2;
     T1 = c[0] * Im1;
     const double e1l = E1 * i2l;
@@ -218,10 +241,11 @@ __device__ __forceinline__ double range_eval(double a, double b, const double (&
       T2 = fma(wpsi, p, T2);
       T1 = fma(wpsi * t, p, T1);
     }
-    F0 = J1 * rcp(J0);
+    f0n = J1;
+    f0d = J0;
   }
   double F = T1 * rcp(T2);
-  if (!(T2 > 0.0) || !isfinite(F)) F = F0;
+  if (!(T2 > 0.0) || !isfinite(F)) F = f0n * rcp(f0d);
   if (flags & 1u) F = fmin(fmax(F, 0.0), 1.0);
   return fma(delta, F, da);
 }
