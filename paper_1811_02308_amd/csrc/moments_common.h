@@ -137,6 +137,34 @@ __device__ __forceinline__ void fused_pixel(const double (&m)[N + 1], float a, f
                                                      fz.flags)));
 }
 
+// P_k(z) = a_k z P_{k-1}(z) - b_k P_{k-2}(z), a_k = (2k-1)/k, b_k = (k-1)/k
+// (the three-term recurrence with its divisions folded into constants).
+struct LegRec {
+  double a[kNMax + 1];
+  double b[kNMax + 1];
+  constexpr LegRec() : a{}, b{} {
+    for (int k = 2; k <= kNMax; ++k) {
+      a[k] = (2.0 * k - 1.0) / k;
+      b[k] = (k - 1.0) / k;
+    }
+  }
+};
+
+// Adds wt * P_k(z), k = 1..N, to acc[1..N].
+template <int N>
+__device__ __forceinline__ void add_legendre(double z, double wt, double (&acc)[N + 1]) {
+  constexpr LegRec LR{};
+  double p0 = 1.0, p1 = z;
+  acc[1] = fma(wt, p1, acc[1]);
+#pragma unroll
+  for (int k = 2; k <= N; ++k) {
+    const double p2 = fma(LR.a[k] * z, p1, -LR.b[k] * p0);
+    acc[k] = fma(wt, p2, acc[k]);
+    p0 = p1;
+    p1 = p2;
+  }
+}
+
 // Direct evaluation of a~_k = sum_j omega_j P_k(z_j) for one pixel (y, x),
 // z_j = (f(i-j) - mid) / half, by the whole wave: lanes split the window's
 // taps, each evaluates P_1..P_N by the three-term recurrence, and the
@@ -157,16 +185,7 @@ __device__ __forceinline__ void direct_legendre(const float* __restrict__ img, l
     const int dy = t / w - R, dx = t - (t / w) * w - R;
     const int yy = min(max(y + dy, 0), H - 1), xx = min(max(x + dx, 0), W - 1);
     const double z = ((double)img[(long long)yy * pitch + xx] - mid) * ih;
-    const double wt = wts ? wts[dy + R] * wts[dx + R] : 1.0;
-    double p0 = 1.0, p1 = z;
-    acc[1] = fma(wt, p1, acc[1]);
-#pragma unroll
-    for (int k = 2; k <= N; ++k) {
-      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-      acc[k] = fma(wt, p2, acc[k]);
-      p0 = p1;
-      p1 = p2;
-    }
+    add_legendre<N>(z, wts ? wts[dy + R] * wts[dx + R] : 1.0, acc);
   }
 #pragma unroll
   for (int k = 1; k <= N; ++k) {
@@ -193,16 +212,7 @@ __device__ __forceinline__ void direct_legendre_lane(const float* __restrict__ i
     const double wy = wts ? wts[dy + R] : 1.0;
     for (int dx = -R; dx <= R; ++dx) {
       const double z = ((double)row[min(max(x + dx, 0), W - 1)] - mid) * ih;
-      const double wt = wts ? wy * wts[dx + R] : 1.0;
-      double p0 = 1.0, p1 = z;
-      acc[1] = fma(wt, p1, acc[1]);
-#pragma unroll
-      for (int k = 2; k <= N; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-        acc[k] = fma(wt, p2, acc[k]);
-        p0 = p1;
-        p1 = p2;
-      }
+      add_legendre<N>(z, wts ? wy * wts[dx + R] : 1.0, acc);
     }
   }
 #pragma unroll
