@@ -132,12 +132,12 @@ __device__ __forceinline__ double wave_origin(const float* __restrict__ alpha,
 }
 
 // Origin of the box kernel's power sums: the mid-range of the input values
-// sampled on an 8 x 8 grid over the wave's output tile. It depends on the
-// input only, so the stack is the same whether the kernel takes the window
-// bounds itself or reads them.
+// sampled on an 8 x 8 grid over the wave's output tile (their range in
+// `span`). It depends on the input only, so the stack is the same whether
+// the kernel takes the window bounds itself or reads them.
 __device__ __forceinline__ double input_origin(const float* __restrict__ img, long long pitch,
                                                int y0, int y1, int xo, int O, int W, int lane,
-                                               const FinMinMax& fm) {
+                                               const FinMinMax& fm, double& span) {
   const int gy = lane >> 3, gx = lane & 7;
   const int yy = min(y0 + (gy * (y1 - 1 - y0)) / 7, y1 - 1);
   const int xx = min(xo + (gx * (O - 1)) / 7, W - 1);
@@ -148,6 +148,7 @@ __device__ __forceinline__ double input_origin(const float* __restrict__ img, lo
     lo = fm.min(lo, __shfl_xor(lo, off, kWave));
     hi = fm.max(hi, __shfl_xor(hi, off, kWave));
   }
+  span = (double)hi - (double)lo;
   return 0.5 * ((double)lo + (double)hi);
 }
 
@@ -159,14 +160,28 @@ __device__ __forceinline__ double input_origin(const float* __restrict__ img, lo
 //
 // The conditioning test rho^N <= cond_max, rho = |mid|/half + 1, is taken as
 // |mid| <= dmax half with dmax = cond_max^(1/N) - 1 (computed once per wave).
+// A pixel that fails it is still accepted when wide > 0 and
+// rho^N (beta - alpha) <= wide: the shift's rounding grows like rho^N, and
+// it reaches the output scaled by the window's range beta - alpha (g^ =
+// alpha + (beta - alpha) F), so with wide = cond_max times the range of
+// the wave's input samples no pixel's error bound exceeds that of a window
+// as wide as the samples at rho^N = cond_max. (Only the FP32 stack uses
+// it; the rarely taken branch costs nothing on images without such
+// pixels.)
 template <int N>
 __device__ __forceinline__ bool legendre_from_sums(double (&m)[N + 1], float a, float b,
                                                    double c, double dmax, double area,
-                                                   double inv_area) {
+                                                   double inv_area, double wide) {
   constexpr LegTable LT{};
   const double mid = 0.5 * ((double)a + (double)b) - c;
   const double half = 0.5 * ((double)b - (double)a);
-  if (!(fabs(mid) <= dmax * half)) return true;
+  if (!(fabs(mid) <= dmax * half)) {
+    const double rho = fabs(mid) / half + 1.0;
+    double rn = rho;
+#pragma unroll
+    for (int k = 1; k < N; ++k) rn *= rho;
+    if (!(rn * ((double)b - (double)a) <= wide)) return true;
+  }
   const double ih = rcp(half);
   const double s = -mid;
   m[0] = area;
@@ -258,7 +273,10 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
   const int xo = strip * g.O;            // first output column of the strip
   const int ow = min(g.O, W - xo);       // its output columns
   const int xs = xo - g.Rpad;            // padded column 0
-  const double c = input_origin(img, pitch, y0, y1, xo, g.O, W, lane, fm);
+  double span;
+  const double c = input_origin(img, pitch, y0, y1, xo, g.O, W, lane, fm, span);
+  // width-aware acceptance of ill-conditioned shifts (FP32 stack only)
+  const double wide = sizeof(TS) == 4 ? cond_max * span : 0.0;
   double (*const shw)[kStripSlots] = sh[wv];
   if (lane < N) shw[lane][kZeroSlot] = 0.0;
 
@@ -377,7 +395,7 @@ __global__ __launch_bounds__(kBoxWaves * kWave) void moments_box(
 #pragma unroll
       for (int k = 0; k < N; ++k) m[k + 1] = shw[k][pidx(eh)] - shw[k][pidx(el)];
       const bool flat = a == b;
-      const bool bad = legendre_from_sums<N>(m, a, b, c, dmax, area, inv_area) && !flat;
+      const bool bad = legendre_from_sums<N>(m, a, b, c, dmax, area, inv_area, wide) && !flat;
       if (flat) {
 #pragma unroll
         for (int k = 1; k <= N; ++k) m[k] = 0.0;
