@@ -175,7 +175,7 @@ int abf_stack_kernel(int h, int w, int kernel_kind, int rho, int N, int precisio
  * abf_fast_fused -- 1 if abf_fast (and abf_fast_strided, and the shared
  * launches of abf_fast_batched) run the moment and range stages of
  * Algorithm 1 fused in one kernel for these arguments: the box kernel on
- * the mixed path at rho <= 8, where the fused kernel was measured faster on
+ * the mixed path at rho <= 32, where the fused kernel was measured faster on
  * MI355X. 0 for the stack path and for invalid arguments. Host only.
  */
 int abf_fast_fused(int h, int w, int kernel_kind, int rho, int N, int precision);

@@ -121,13 +121,15 @@ def test_stack_single_pass_query():
 
 
 def test_fast_fused_query():
-    """abf_fast_fused: the box kernel on the mixed path at rho <= 8 runs the
+    """abf_fast_fused: the box kernel on the mixed path at rho <= 32 runs the
     moment and range stages fused; everything else, and invalid arguments,
     the stack path."""
     L = abf.lib()
     assert L.abf_fast_fused(4096, 4096, 0, 5, 8, 1) == 1
     assert L.abf_fast_fused(4096, 4096, 0, 8, 5, 1) == 1
-    assert L.abf_fast_fused(4096, 4096, 0, 9, 5, 1) == 0
+    assert L.abf_fast_fused(4096, 4096, 0, 20, 8, 1) == 1
+    assert L.abf_fast_fused(4096, 4096, 0, 32, 5, 1) == 1
+    assert L.abf_fast_fused(4096, 4096, 0, 33, 5, 1) == 0
     assert L.abf_fast_fused(4096, 4096, 0, 5, 8, 0) == 0          # FP64
     assert L.abf_fast_fused(4096, 4096, 1, 5, 8, 1) == 0          # Gaussian
     assert L.abf_fast_fused(4096, 4096, 2, 5, 8, 1) == 0          # recursive

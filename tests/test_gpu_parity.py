@@ -435,12 +435,13 @@ def test_fused_equals_stack_path(torch, abf, precision, kernel, R, N):
 
 
 FUSED_EDGE = [((1, 1), 0, 1), ((1, 1), 8, 8), ((1, 300), 5, 6), ((300, 1), 5, 6), ((5, 7), 8, 8),
-              ((70, 90), 0, 6), ((70, 90), 1, 7), ((257, 513), 8, 1), ((64, 250), 4, 5)]
+              ((70, 90), 0, 6), ((70, 90), 1, 7), ((257, 513), 8, 1), ((64, 250), 4, 5),
+              ((90, 450), 20, 8), ((41, 37), 32, 6), ((200, 200), 13, 5)]
 
 
 @pytest.mark.parametrize("shape,R,N", FUSED_EDGE)
 def test_fused_default_edges(torch, abf, shape, R, N):
-    """abf_fast's fused path (box kernel, mixed, rho <= 8) on single pixels,
+    """abf_fast's fused path (box kernel, mixed, rho <= 32) on single pixels,
     single rows and columns, rho = 0 and 1, N = 1, and strips with a partial
     last chunk: equal to the stack path bit for bit, and within the mixed
     bar of the oracle at every pixel."""
@@ -459,10 +460,10 @@ def test_fused_default_edges(torch, abf, shape, R, N):
     assert np.max(np.abs(out.cpu().numpy().astype(np.float64) - want)) < TOL["mixed"]
 
 
-@pytest.mark.parametrize("R,N", [(5, 8), (8, 6), (3, 5)])
+@pytest.mark.parametrize("R,N", [(5, 8), (8, 6), (3, 5), (20, 8)])
 def test_fused_default_equals_stack_path_4096(torch, abf, vor4096, R, N):
     """At 4096^2 the box kernel's segment geometry fills the device in whole
-    rounds of waves; where abf_fast takes the fused path (mixed, rho <= 8)
+    rounds of waves; where abf_fast takes the fused path (mixed, rho <= 32)
     the geometry is sized for both instantiations, so abf_fast's output
     equals the stack path's bit for bit on a full-size image too."""
     assert abf.fast_fused(4096, 4096, "box", R, N, "mixed")
