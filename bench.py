@@ -53,7 +53,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
 DEFAULT_WORKLOAD = "voronoi4096_box5_n8"
 PREWARM_STEPS = 300           # untimed steps per path before the counted warm-up
-MAX_POOL = 16                 # host processes of the all-core CPU leg (the GPU machine's CPU share)
+MAX_POOL = 16                 # host processes of the all-core CPU leg (at most one per core, and no more than 16)
 N_STREAMS = 2                  # images in flight in the timed steps (default of --streams)
 
 
