@@ -240,6 +240,27 @@ def test_edge_sigma_inf_and_theta_far(torch, abf, precision):
     assert np.max(np.abs(got - ref)) < TOL[precision]
 
 
+@pytest.mark.parametrize("amp", [0.05, 0.08])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_narrow_windows_far_from_origin(torch, abf, precision, amp):
+    """Plateaus at 90 and 110 (alternating every 48 columns, so every wave's
+    samples span both) with noise of +-amp: the windows inside a plateau
+    are about 2 amp wide and 10 away from the wave's origin (rho about 200
+    and 125), so their shift is ill-conditioned at N = 6 and 7. On the FP32
+    stack they are taken through the width-aware acceptance or recomputed
+    from their windows, on the FP64 path recomputed; every pixel within the
+    bar of the oracle."""
+    h, w = 64, 400
+    rng = np.random.default_rng(int(amp * 1000))
+    base = np.where((np.arange(w) // 48) % 2 == 0, 90.0, 110.0)
+    f = (base[None, :] + rng.uniform(-amp, amp, (h, w))).astype(np.float32)
+    sg = smooth_field(np.random.default_rng(2), h, w, 0.05, 30.0)
+    for N in (6, 7):
+        got = abf.fast(dev(torch, f), dev(torch, sg), rho=5, N=N, precision=precision)
+        ref = oracle.fast_abf(f, None, sg, "box", 5, N)
+        assert np.max(np.abs(got.cpu().numpy().astype(np.float64) - ref)) < TOL[precision], N
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_edge_window_larger_than_image(torch, abf, precision):
     f = rect_scene(9, 9, 23, n_rect=3, noise=10, side_lo=2, side_hi=6)
