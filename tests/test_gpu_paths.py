@@ -208,6 +208,37 @@ def test_texture_full_size_first_pass_sampled(torch, abf, texture, precision):
         assert np.max(np.abs(got - ref)) < TOL[precision], c
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_texture_full_size_third_pass_sampled(torch, abf, texture, precision):
+    """The texture workload's third pass at full size. Its input (two passes
+    of smoothing) is nearly flat in places, so many windows are narrow and
+    far from their wave's origin: their shifts are ill-conditioned and are
+    accepted by the FP32 stack's width-aware rule or recomputed from their
+    windows. Sampled pixels of three planes, plus each plane's 64 windows of
+    smallest non-zero range, against the oracle fed the GPU's pass-3 input
+    and sigma map."""
+    from scipy.ndimage import maximum_filter, minimum_filter
+    fr = texture["frames"]
+    n, h, w = fr.shape
+    R, N, sr = texture["R"], texture["N"], texture["sigma_rule"]
+    x = torch.from_numpy(fr).cuda()
+    x3 = abf.texture_filter(x, 2, R, N, precision=precision, **sr).float()
+    sig = abf.sigma_local_std(x3, **sr)
+    y = abf.fast_strided(x3, sig, kernel="box", rho=R, N=N, precision=precision)
+    torch.cuda.synchronize()
+    for c in (0, 41, n - 1):
+        f3, sc = x3[c].cpu().numpy(), sig[c].cpu().numpy()
+        d = (maximum_filter(f3, 2 * R + 1, mode="nearest").astype(np.float64)
+             - minimum_filter(f3, 2 * R + 1, mode="nearest"))
+        flat = np.argsort(np.where(d > 0, d, np.inf), axis=None)[:64]
+        ys, xs = edge_samples(h, w, 150, seed=100 + c)
+        ys = np.concatenate([ys, flat // w])
+        xs = np.concatenate([xs, flat % w])
+        ref = oracle.fast_abf(f3, None, sc, "box", R, N, pixels=(ys, xs))
+        got = y[c].cpu().numpy().astype(np.float64)[ys, xs]
+        assert np.max(np.abs(got - ref)) < TOL[precision], c
+
+
 # ----------------------------------------------------------------- large images
 @pytest.fixture(scope="module")
 def large_image():
