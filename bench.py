@@ -99,7 +99,8 @@ def stage_model(h, w, kernel, R, N, prec_bytes, theta_given):
         # window bounds and moments in one kernel: f in; alpha, beta, a~ out
         "stack": dict(bytes=px * (4 + 8 + N * b), flops=px * (conv_flops + shift_flops)),
         "range": dict(bytes=px * (8 + N * b + tb + 4 + b), flops=px * range_flops),
-        # fused: f, alpha, beta, theta, sigma in; g^ out (the stack never leaves the CU)
+        # fused: f, theta, sigma in, alpha and beta in (or, where the kernel
+        # takes the bounds itself, out); g^ out (the stack never leaves the CU)
         "moments_range": dict(bytes=px * (4 + 8 + tb + 4 + b),
                               flops=px * (conv_flops + shift_flops + range_flops)),
     }
@@ -325,13 +326,20 @@ def main():
     streams = [torch.cuda.Stream() for _ in range(n_streams)]
 
     def make_path(prec, fused):
+        # fused with a moment kernel that takes the window bounds itself (the
+        # Gaussian tile kernel): abf_fast runs the whole filter as one kernel
+        one = fused and single
         bufs = []
         for _ in range(n_streams):
-            bufs.append((torch.empty(abf.stack_bytes(H, W, N, prec), dtype=torch.uint8, device="cuda"),
+            sb = (abf.workspace_bytes(H, W, R, N, prec, kernel) if one
+                  else abf.stack_bytes(H, W, N, prec))
+            bufs.append((torch.empty(sb, dtype=torch.uint8, device="cuda"),
                          torch.empty(abf.lib().abf_scratch_bytes(H, W, R), dtype=torch.uint8, device="cuda"),
                          torch.empty((H, W), dtype=torch.float32 if prec == "mixed" else torch.float64,
                                      device="cuda")))
-        if fused:
+        if one:
+            names = ["moments_range"]
+        elif fused:
             names = ["minmax", "moments_range"]
         else:
             names = ["stack", "range"] if single else ["minmax", "moments", "range"]
@@ -340,6 +348,12 @@ def main():
             stack, scr, out = bufs[j]
             if ev is not None:
                 ev[0].record()
+            if one:
+                abf.fast(fd, sd, theta=td, kernel=kernel, rho=R, N=N, sigma_s=ss, precision=prec,
+                         out=out, workspace=stack, stream=stream)
+                if ev is not None:
+                    ev[1].record()
+                return
             if fused or not single:
                 abf.minmax_into_stack(fd, stack, R, N, prec, workspace=scr, stream=stream)
                 if ev is not None:
@@ -462,13 +476,15 @@ def main():
     # whole path at the roofline: the algorithmic bytes of one step (read f,
     # theta-or-f and sigma, write the output, write and read once each plane
     # the path keeps in HBM: the whole stack, or on the fused path the window
-    # bounds only) over the step's wall time
+    # bounds only; where one kernel runs the whole filter the bounds are
+    # written and never read back) over the step's wall time
     planes = 2 if fuses["mixed"] else N + 2
-    path_bytes = H * W * (16 + 8 * planes)
+    bpp = 16 + 8 * planes - (8 if fuses["mixed"] and single else 0)
+    path_bytes = H * W * bpp
     path_gbs = path_bytes / (ms_m * 1e-3) / 1e9
     whole = {"bound": "hbm", "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(path_gbs / HBM_PEAK_GBS, 4), "bytes_per_step": path_bytes,
-             "bytes_per_pixel": 16 + 8 * planes}
+             "bytes_per_pixel": bpp}
     if fuses["mixed"]:
         # the same rate against the stack formulation's algorithmic bytes (the
         # whole moment stack written and read once): what the fused path

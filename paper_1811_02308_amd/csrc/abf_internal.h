@@ -233,9 +233,9 @@ struct FuseSpec {
 // fuse != nullptr also evaluates the range stage per pixel and writes the
 // filtered output (only where moments_fusable() holds); the result equals
 // launch_range() on the stack. bounds = true (only where
-// moments_take_bounds() holds, without fuse) computes the window bounds in
-// the same kernel and writes them to alpha/beta; the stack is then
-// identical to launch_minmax() followed by launch_moments().
+// moments_take_bounds() holds) computes the window bounds in the same
+// kernel and writes them to alpha/beta; the stack (and, with fuse, the
+// output) is then identical to launch_minmax() followed by launch_moments().
 hipError_t launch_moments(const float* img, long long pitch, int h, int w,
                           int kernel_kind, double sigma_s, int rho, int N, int prec,
                           float* alpha, float* beta, long long sp,

@@ -265,12 +265,36 @@ abf_status abf_moments_range(const float* img, const float* theta, const float* 
 // abf::fast_fuses() holds, else the stack path (moment stack, then range
 // stage). `stack` holds the image's (or batch's) stacks, `scratch` the
 // bounds scratch.
+// The Gaussian tile kernel on the mixed path, where it takes the window
+// bounds itself: one kernel for the whole filter (bounds, moments and the
+// range stage), its output equal to the stack path's bit for bit.
+static bool fast_one_kernel(int kernel_kind, int rho, int N, int precision, int h, int w) {
+  return kernel_kind == ABF_KERNEL_GAUSSIAN && precision == ABF_PREC_MIXED && N >= 1 &&
+         abf::moments_take_bounds(kernel_kind, rho, N, h, w) &&
+         abf::moments_fusable(kernel_kind, rho, N, h, w);
+}
+
 static abf_status fast_stages(const float* img, const float* theta, const float* sigma, int h,
                               int w, long long pitch, int kernel_kind, double sigma_s, int rho,
                               int N, int precision, unsigned flags, char* stack, void* scratch,
                               void* out, long long out_pitch, hipStream_t s,
                               const abf::Batch& b) {
   const unsigned rflags = flags & ABF_FLAG_CLAMP;
+  if (fast_one_kernel(kernel_kind, rho, N, precision, h, w)) {
+    const long long sp = abf_stack_pitch(w);
+    float* alpha = reinterpret_cast<float*>(stack);
+    float* beta = reinterpret_cast<float*>(stack + abf_stack_plane_offset(h, w, N, precision, 1));
+    void* mom = stack + abf_stack_plane_offset(h, w, N, precision, 2);
+    abf::FuseSpec fs;
+    fs.theta = theta ? theta : img;
+    fs.sigma = sigma;
+    fs.tpitch = pitch;
+    fs.out = out;
+    fs.opitch = out_pitch;
+    fs.flags = rflags;
+    return hip_status(abf::launch_moments(img, pitch, h, w, kernel_kind, sigma_s, rho, N, 1,
+                                          alpha, beta, sp, mom, sp * h, s, b, &fs, true));
+  }
   if (N > 0 && abf::fast_fuses(kernel_kind, rho, N, precision == ABF_PREC_MIXED ? 1 : 0)) {
     const long long sp = abf_stack_pitch(w);
     float* alpha = reinterpret_cast<float*>(stack);
@@ -291,7 +315,10 @@ int abf_fast_fused(int h, int w, int kernel_kind, int rho, int N, int precision)
   if (h < 1 || w < 1 || rho < 0 || rho > ABF_RHO_MAX || N < 1 || N > ABF_N_MAX ||
       !stack_kind_ok(kernel_kind) || !prec_ok(precision))
     return 0;
-  return abf::fast_fuses(kernel_kind, rho, N, precision == ABF_PREC_MIXED ? 1 : 0) ? 1 : 0;
+  return (abf::fast_fuses(kernel_kind, rho, N, precision == ABF_PREC_MIXED ? 1 : 0) ||
+          fast_one_kernel(kernel_kind, rho, N, precision, h, w))
+             ? 1
+             : 0;
 }
 
 abf_status abf_fast(const float* img, const float* theta, const float* sigma, int h, int w,

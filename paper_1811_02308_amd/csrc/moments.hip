@@ -479,10 +479,6 @@ __global__ __launch_bounds__(256) void moments_gauss_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R, int TX, double inv2s2,
     float* __restrict__ alpha, float* __restrict__ beta, long long sp,
     TS* __restrict__ mom, long long plane, double cond_max, Batch bt, FuseArgs fz) {
-  // (the fused range stage is used with bounds from the stack: with the
-  // bounds taken here as well the kernel was measured slower than the two
-  // kernels of the stack path)
-  static_assert(!(FUSED && BOUNDS), "the fused range stage reads the bounds from the stack");
   const FinMinMax fm;      // (window bounds)
   // dynamic LDS: [N][kTY][ES] doubles (vertical sums), the tap weights
   // (tile_wext_len(R) doubles), then (BOUNDS) [kTY][ES] float2 (min, max);
@@ -1194,7 +1190,7 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
                             double sigma_s, int R, float* alpha, float* beta,
                             long long sp, TS* mom, long long plane, hipStream_t stream,
                             const Batch& b, const FuseSpec* fs, bool bounds) {
-  if (bounds && (fs || !moments_take_bounds(kind, R, N, h, w))) return hipErrorNotSupported;
+  if (bounds && !moments_take_bounds(kind, R, N, h, w)) return hipErrorNotSupported;
   // resident waves of the box kernel on this device (occupancy x CUs). The
   // segment geometry depends on the image, radius and device only (not on
   // the batch size or on fusion), so an image gets bit-identical moments
@@ -1291,7 +1287,9 @@ hipError_t launch_moments_t(const float* img, long long pitch, int h, int w, int
 #define ABF_TILE(F, S, B)                                                                       \
   hipLaunchKernelGGL((moments_gauss_tile<N, TS, F, S, B>), tg, dim3(256), lds, stream, img, pitch, \
                      h, w, R, tx, i2, alpha, beta, sp, mom, plane, cond_max, b, fz)
-    if (fs) {
+    if (fs && bounds) {
+      if (narrow) ABF_TILE(true, kESNarrow, true); else ABF_TILE(true, 256, true);
+    } else if (fs) {
       if (narrow) ABF_TILE(true, kESNarrow, false); else ABF_TILE(true, 256, false);
     } else if (bounds) {
       if (narrow) ABF_TILE(false, kESNarrow, true); else ABF_TILE(false, 256, true);

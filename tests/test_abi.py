@@ -122,8 +122,10 @@ def test_stack_single_pass_query():
 
 def test_fast_fused_query():
     """abf_fast_fused: the box kernel on the mixed path at rho <= 32 runs the
-    moment and range stages fused; everything else, and invalid arguments,
-    the stack path."""
+    moment and range stages fused, and so does the Gaussian tile kernel on
+    the mixed path where it takes the window bounds itself (one kernel for
+    the whole filter); everything else, and invalid arguments, the stack
+    path."""
     L = abf.lib()
     assert L.abf_fast_fused(4096, 4096, 0, 5, 8, 1) == 1
     assert L.abf_fast_fused(4096, 4096, 0, 8, 5, 1) == 1
@@ -131,7 +133,10 @@ def test_fast_fused_query():
     assert L.abf_fast_fused(4096, 4096, 0, 32, 5, 1) == 1
     assert L.abf_fast_fused(4096, 4096, 0, 33, 5, 1) == 0
     assert L.abf_fast_fused(4096, 4096, 0, 5, 8, 0) == 0          # FP64
-    assert L.abf_fast_fused(4096, 4096, 1, 5, 8, 1) == 0          # Gaussian
+    assert L.abf_fast_fused(4096, 4096, 1, 5, 8, 1) == 1          # Gaussian tile, bounds taken
+    assert L.abf_fast_fused(1024, 1024, 1, 15, 6, 1) == 1
+    assert L.abf_fast_fused(4096, 4096, 1, 10, 6, 1) == 0         # matrix-core stack
+    assert L.abf_fast_fused(1024, 1024, 1, 15, 6, 0) == 0         # FP64
     assert L.abf_fast_fused(4096, 4096, 2, 5, 8, 1) == 0          # recursive
     assert L.abf_fast_fused(64, 64, 0, 3, 0, 1) == 0              # N = 0: bounds only
     assert L.abf_fast_fused(0, 64, 0, 3, 5, 1) == 0

@@ -481,6 +481,39 @@ def test_fused_default_edges(torch, abf, shape, R, N):
     assert np.max(np.abs(out.cpu().numpy().astype(np.float64) - want)) < TOL["mixed"]
 
 
+GAUSS_ONE = [((1, 1), 3, 6), ((7, 300), 5, 8), ((70, 90), 15, 6), ((130, 257), 20, 5),
+             ((64, 200), 1, 1), ((33, 47), 40, 7), ((600, 520), 12, 6)]
+
+
+@pytest.mark.parametrize("shape,R,N", GAUSS_ONE)
+def test_gaussian_one_kernel_default(torch, abf, shape, R, N):
+    """abf_fast's Gaussian path on the mixed path, where the tile kernel
+    takes the window bounds itself: one kernel for the whole filter (bounds,
+    moments, range stage). Equal to the stack path bit for bit and within
+    the mixed bar of the oracle at every pixel; single pixels and rows,
+    ragged tiles, both LDS strides (R up to 16 and above)."""
+    h, w = shape
+    assert abf.fast_fused(h, w, "gaussian", R, N, "mixed")
+    f = rect_scene(900 + R + N, h, w, n_rect=4, noise=7.0, side_lo=1, side_hi=max(2, min(h, w)))
+    sg = smooth_field(np.random.default_rng(R + 5 * N), h, w, 6, 45)
+    th = (f + smooth_field(np.random.default_rng(N + 1), h, w, -10, 10)).astype(np.float32)
+    img, sgd, thd = dev(torch, f), dev(torch, sg), dev(torch, th)
+    out = abf.fast(img, sgd, theta=thd, kernel="gaussian", rho=R, N=N, precision="mixed")
+    st = abf.moment_stack(img, kernel="gaussian", rho=R, N=N, precision="mixed")
+    ref = abf.range_from_stack(st, sgd, img=img, theta=thd, N=N, precision="mixed")
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    if h * w * (2 * R + 1) ** 2 <= 3e7:
+        want = oracle.fast_abf(f, th, sg, "gaussian", R, N)
+        assert np.max(np.abs(out.cpu().numpy().astype(np.float64) - want)) < TOL["mixed"]
+    else:
+        rng = np.random.default_rng(R)
+        ys, xs = rng.integers(0, h, 800), rng.integers(0, w, 800)
+        want = oracle.fast_abf(f, th, sg, "gaussian", R, N, pixels=(ys, xs))
+        got = out.cpu().numpy().astype(np.float64)[ys, xs]
+        assert np.max(np.abs(got - want)) < TOL["mixed"]
+
+
 @pytest.mark.parametrize("R,N", [(5, 8), (8, 6), (3, 5), (20, 8)])
 def test_fused_default_equals_stack_path_4096(torch, abf, vor4096, R, N):
     """At 4096^2 the box kernel's segment geometry fills the device in whole
