@@ -175,8 +175,11 @@ int abf_stack_kernel(int h, int w, int kernel_kind, int rho, int N, int precisio
  * abf_fast_fused -- 1 if abf_fast (and abf_fast_strided, and the shared
  * launches of abf_fast_batched) run the moment and range stages of
  * Algorithm 1 fused in one kernel for these arguments: the box kernel on
- * the mixed path at rho <= 32, where the fused kernel was measured faster on
- * MI355X. 0 for the stack path and for invalid arguments. Host only.
+ * the mixed path at rho <= 32, and the Gaussian kernel on the mixed path
+ * wherever its tile kernel builds the stack (there the same kernel takes
+ * the window bounds as well: the whole filter in one launch), where the
+ * fused kernels were measured faster on MI355X. 0 for the stack path and
+ * for invalid arguments. Host only.
  */
 int abf_fast_fused(int h, int w, int kernel_kind, int rho, int N, int precision);
 
@@ -236,7 +239,9 @@ abf_status abf_moments_range(const float* img, const float* theta, const float* 
  * abf_moment_stack into the front of `workspace`, then abf_range; or, where
  * abf_fast_fused() is 1, abf_minmax into the stack's bounds planes and then
  * abf_moments_range (moments and range stage in one kernel, the moment
- * planes never written). Both give the same output bit for bit.
+ * planes never written), the Gaussian tile kernel writing the bounds
+ * planes itself in that same kernel instead. All give the same output bit
+ * for bit.
  * workspace >= abf_workspace_bytes(h, w, rho, N, precision), 256-byte
  * aligned. theta, sigma share `pitch` with img. Only ABF_FLAG_CLAMP of
  * `flags` is used.
