@@ -113,10 +113,24 @@ __global__ __launch_bounds__(kThreads) void vh_rows(
 //   vertical: the same on columns of the horizontal result, 8 output rows
 //     per thread, written straight to alpha/beta.
 // No intermediate leaves the workgroup; f is read once (+ halo from L2).
-constexpr int kMTX = 64, kMTY = 32, kTileRMax = 24, kHS = kMTX + 1;
-// horizontal items per thread: (kMTY + 2 kTileRMax) kMTX / 8 <= kHItems kThreads
+// Output tile MTX x MTY: 64 x 32, or 32 x 32 where the wider tile's LDS
+// would exceed kTileLdsSmall (rho >= 8): a bounds kernel of that size
+// still fits on a CU beside the fused box kernel's eight waves (17 KiB of
+// LDS each), so the two images in flight overlap it instead of queueing it.
+constexpr int kTileRMax = 24;
+constexpr size_t kTileLdsSmall = 24 * 1024;
+// horizontal items per thread: (MTY + 2 kTileRMax) MTX / 8 <= kHItems kThreads
 constexpr int kHItems = 3;
-static_assert((kMTY + 2 * kTileRMax) * (kMTX / 8) <= kHItems * kThreads, "horizontal items per thread");
+static_assert((32 + 2 * kTileRMax) * (64 / 8) <= kHItems * kThreads, "horizontal items per thread");
+template <int MTX>
+__host__ __device__ constexpr int tile_hs() { return MTX + 1; }
+template <int MTX, int MTY>
+size_t tile_lds_bytes(int R) {
+  const int EX = MTX + 2 * R, EY = MTY + 2 * R, XS = EX | 1;
+  const size_t tile_b = (size_t)EY * XS * sizeof(float);
+  const size_t hres_b = (size_t)EY * tile_hs<MTX>() * sizeof(float2);
+  return tile_b > hres_b ? tile_b : hres_b;
+}
 
 template <typename Get>
 __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&mx)[8],
@@ -168,6 +182,7 @@ __device__ __forceinline__ void slide8(Get get, int R, float (&mn)[8], float (&m
   }
 }
 
+template <int kMTX, int kMTY>
 __global__ __launch_bounds__(kThreads) void minmax_tile(
     const float* __restrict__ img, long long pitch, int H, int W, int R,
     float* __restrict__ out_a, float* __restrict__ out_b, long long op, Batch bt) {
@@ -184,6 +199,7 @@ __global__ __launch_bounds__(kThreads) void minmax_tile(
   // different banks. The horizontal result takes the tile's place once the
   // tile has been read (it is held in registers across a barrier), so the
   // LDS footprint is the larger of the two, not their sum.
+  constexpr int kHS = tile_hs<kMTX>();
   const int EX = kMTX + 2 * R, EY = kMTY + 2 * R;
   const int XS = EX | 1;
   float* tile = lds;                                       // EY x XS
@@ -253,14 +269,19 @@ hipError_t launch_minmax(const float* img, long long pitch, int h, int w, int rh
                          float* alpha, float* beta, long long out_pitch,
                          void* scratch, hipStream_t stream, const Batch& b) {
   if (rho <= kTileRMax) {
-    // clamping of the padded tile makes any radius exact; use rho itself
-    dim3 grid((w + kMTX - 1) / kMTX, (h + kMTY - 1) / kMTY, b.n);
-    const int EX = kMTX + 2 * rho, EY = kMTY + 2 * rho, XS = EX | 1;
-    // the padded tile, then the horizontal result in the same bytes
-    const size_t tile_b = (size_t)EY * XS * sizeof(float), hres_b = (size_t)EY * kHS * sizeof(float2);
-    const size_t lds = tile_b > hres_b ? tile_b : hres_b;
-    hipLaunchKernelGGL(minmax_tile, grid, dim3(kThreads), lds, stream, img, pitch, h, w, rho,
-                       alpha, beta, out_pitch, b);
+    // clamping of the padded tile makes any radius exact; use rho itself.
+    // The padded tile, then the horizontal result in the same bytes.
+    const size_t lds_wide = tile_lds_bytes<64, 32>(rho);
+    if (lds_wide <= kTileLdsSmall) {
+      dim3 grid((w + 63) / 64, (h + 31) / 32, b.n);
+      hipLaunchKernelGGL((minmax_tile<64, 32>), grid, dim3(kThreads), lds_wide, stream, img, pitch,
+                         h, w, rho, alpha, beta, out_pitch, b);
+    } else {
+      dim3 grid((w + 31) / 32, (h + 31) / 32, b.n);
+      const size_t lds_small = tile_lds_bytes<32, 32>(rho);
+      hipLaunchKernelGGL((minmax_tile<32, 32>), grid, dim3(kThreads), lds_small, stream, img, pitch,
+                         h, w, rho, alpha, beta, out_pitch, b);
+    }
     return hipGetLastError();
   }
   // The window clipped to the image is the same for any radius >= dim - 1.
